@@ -1,0 +1,160 @@
+#!/usr/bin/env python3
+"""Forward-solver benchmark of the Bernstein-Bezier DG path on one MI355X.
+
+Default workload (the forward-throughput configuration): the unit cube split
+into 16^3 x 6 = 24,576 affine tets with interior vertices jittered by +-10% of
+h (seeded), order N = 5 (Np = 56), fields p,u,v,w, unit wavespeed, rigid
+walls, standing-mode initial pressure, LSRK4 with dt = 0.5 h/(N+1)^2.
+A bench "step" is one LSRK4 time step = five fused stage kernels (volume +
+surface + update each); inputs are resident in HBM before timing starts.
+
+Prints one JSON line: DoF-stage updates/s (4 K Np per stage) for FP64 (the
+headline value), plus the FP32 run on the same workload, the roofline
+placement of the stage kernel, and the FP64 CPU oracle timed on a bounded
+sample on the host cores.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak
+
+
+def algorithmic_bytes_per_element(N, word):
+    """w (16 Np + 16 Nfp + 14) + 20 bytes: read q and res, read the 4 faces'
+    neighbour traces, write q and res; 14 words of geometry, 20 B of indices."""
+    Np = (N + 1) * (N + 2) * (N + 3) // 6
+    Nfp = (N + 1) * (N + 2) // 2
+    return word * (16 * Np + 16 * Nfp + 14) + 20
+
+
+def time_gpu(P, torch, N, mesh, c, q0, dt, steps, warmup, dtype):
+    s = P.Solver(N, mesh, c, dtype=dtype)
+    q = torch.from_numpy(q0).to("cuda", s.torch_dtype)
+    stream = torch.cuda.current_stream()
+    if warmup:
+        s.run(q, dt, warmup, stream=stream)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    s.run(q, dt, steps, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    finite = bool(torch.isfinite(q).all().item())
+    s.close()
+    return ms, finite
+
+
+def cpu_baseline(VX, EToV, c, N, q0, dt, sample_steps):
+    from threadpoolctl import threadpool_info
+
+    from oracle import dg
+    prob = dg.Problem(VX, EToV, N, c)
+    t0 = time.perf_counter()
+    prob.lsrk4(q0, dt, sample_steps)
+    sec = time.perf_counter() - t0
+    threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    K, Np = prob.K, prob.Np
+    return {
+        "value": 4.0 * K * Np * 5 * sample_steps / sec,
+        "unit": "DoF-stage/s",
+        "cores": int(threads),
+        "kind": "oracle",
+        "sample": "%d LSRK4 step(s) = %d stages of the FP64 dense-operator oracle on the full "
+                  "K=%d, N=%d mesh (%.1f s)" % (sample_steps, 5 * sample_steps, K, N, sec),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--config", default="c2", help="named workload (c1..c3)")
+    ap.add_argument("--order", type=int, default=None, help="override N")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-steps", type=int, default=1)
+    ap.add_argument("--no-fp32", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this solver runs on a single GPU; multi-GPU runs (--gpus %d) are not "
+              "supported by this build" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1512_06025_amd as P
+    import workload
+    from paper_1512_06025_amd import ic
+
+    over = {} if args.order is None else {"N": args.order}
+    cfg, VX, EToV, c = workload.build_preset(args.config, **over)
+    N, K, Np, dt = cfg["N"], cfg["K"], cfg["Np"], cfg["dt"]
+    Nfp = (N + 1) * (N + 2) // 2
+    mesh = P.mesh_geometry(VX, EToV)
+    q0 = ic.initial_state(N, VX, EToV, workload.INITIAL_FIELDS[cfg["ic"]])
+
+    stages = 5 * args.steps
+    dof = 4.0 * K * Np
+    ms64, ok64 = time_gpu(P, torch, N, mesh, c, q0, dt, args.steps, args.warmup, "f64")
+    value = dof * stages / (ms64 * 1e-3)
+    stage_us = ms64 * 1e3 / stages
+    bytes_launch = algorithmic_bytes_per_element(N, 8) * K
+    achieved = bytes_launch / (stage_us * 1e-6) / 1e9
+
+    out = {
+        "metric": "DoF-stage updates/s & % HBM roofline (BB vs nodal, FP64/FP32); grad/forward x",
+        "value": value,
+        "unit": "DoF-stage/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms64 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "BB-DG acoustic forward, unit cube %d^3x6 = %d tets%s, N=%d (Np=%d), %s IC, "
+                        "rigid walls, LSRK4 dt=%.6g, %d steps" % (
+                            cfg["n"], K, ", interior vertices jittered +-%g h" % cfg["jitter"] if cfg["jitter"] else "",
+                            N, Np, cfg["ic"], dt, args.steps),
+            "K": K, "N": N, "Np": Np, "Nfp": Nfp, "stages": stages,
+            "parallelism": "single GPU",
+        },
+        "stage_us": stage_us,
+        "finite": ok64,
+        "roofline": {
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+            "kernel": "bb_stage_kernel<N=%d,double,stage>" % N,
+            "bytes_per_launch": bytes_launch,
+            "avg_launch_us": stage_us,
+        },
+    }
+    if not args.no_fp32:
+        ms32, ok32 = time_gpu(P, torch, N, mesh, c, q0, dt, args.steps, args.warmup, "f32")
+        st32 = ms32 * 1e3 / stages
+        a32 = algorithmic_bytes_per_element(N, 4) * K / (st32 * 1e-6) / 1e9
+        out["fp32"] = {"value": dof * stages / (ms32 * 1e-3), "ms_per_step": ms32 / args.steps,
+                       "stage_us": st32, "achieved_GBs": a32, "frac": a32 / HBM_PEAK_GBS, "finite": ok32}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(VX, EToV, c, N, q0, dt, args.cpu_sample_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

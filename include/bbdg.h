@@ -1,0 +1,147 @@
+/*
+ * bbdg.h — C ABI of libbbdg: Bernstein-Bezier discontinuous Galerkin solver
+ * for the first-order acoustic wave equation on affine tetrahedral meshes,
+ * running on AMD Instinct MI355X (gfx950).
+ *
+ * What is computed.  The PDE (1/kappa) p_t + div u = 0, rho u_t + grad p = 0
+ * with rho = 1 and kappa = c^2 constant per element (paper, Section 2), in
+ * the upwind DG discretisation of Section 2 (fluxes with tau_p = 1/{{rho c}},
+ * tau_u = {{rho c}}, {{.}} the arithmetic mean) written in strong form with
+ * the inverse mass matrix applied (the ODE system of Section 3).  The
+ * unknowns are the Bernstein-Bezier coefficients of p, u, v, w on every
+ * element (Section 3.1).  One right-hand-side evaluation is
+ *   volume term:  the sparse barycentric derivative operators of Lemma 1
+ *                 (Section 3.1.1, Appendix A.1) and the chain rule;
+ *   surface term: upwind flux on the face control points, the face operator
+ *                 L_0 and the lift reduction E_L of the factorisation
+ *                 L^f = E_L^f L_0 (Section 3.1.2, Appendix A.3), E_L applied
+ *                 one degree reduction at a time;
+ * and a time step is the five-stage low-storage RK4 of Carpenter and Kennedy
+ * cited in Section 4.2 (volume, surface and update fused in one kernel per
+ * stage).
+ *
+ * Conventions shared by every entry point.
+ *   Orders:      1 <= N <= 9.  Np = (N+1)(N+2)(N+3)/6 coefficients per element
+ *                and field, Nfp = (N+1)(N+2)/2 per face.
+ *   Coefficient order: alpha = (a0,a1,a2,a3), |alpha| = N, a3 slowest, then a2,
+ *                then a1 fastest (a0 = N-a1-a2-a3); bbdg_alpha_table lists it.
+ *                Barycentric coordinate lambda_i belongs to local vertex i of the
+ *                element; B_alpha = N!/alpha! lambda^alpha.
+ *   Faces:       local face f is the face opposite local vertex f.
+ *   Fields:      device arrays of shape (4, K, Np), row-major, in the order
+ *                (p, u, v, w); element-major within a field.  Element type is
+ *                double (BBDG_F64) or float (BBDG_F32) as chosen at create time.
+ *   Geometry:    host array geo of shape (K, 10) double: d(lambda_i)/dx,
+ *                d(lambda_i)/dy, d(lambda_i)/dz for i = 1, 2, 3 (9 values), then
+ *                J = 3 V / 4 (V the element volume; J > 0 required).
+ *   Connectivity: host arrays (K, 4): EToE = neighbour element across face f or
+ *                -1 on the domain boundary; EToF = the neighbour's local face;
+ *                EToO = orientation code 0..5 of the shared face: with
+ *                (a0<a1<a2) the own face's local vertices and (b0<b1<b2) the
+ *                neighbour's, own vertex a_m is neighbour vertex b_pi(m), and
+ *                EToO is the index of (pi(0),pi(1),pi(2)) in the list
+ *                (0,1,2) (0,2,1) (1,0,2) (1,2,0) (2,0,1) (2,1,0).
+ *   Streams:     `stream` is a hipStream_t passed as void* (NULL = default
+ *                stream).  Every device call is stream-ordered and asynchronous;
+ *                only bbdg_destroy synchronises.
+ *   Ownership:   the caller owns every field, work and output buffer; the
+ *                library owns only the device copies of geometry, connectivity
+ *                and operator index tables, allocated in bbdg_create and freed
+ *                in bbdg_destroy.
+ *   Errors:      every int-returning call returns BBDG_OK (0) or a negative
+ *                BBDG_E_* code; nothing throws across the ABI.  Arguments are
+ *                validated before the device is touched.  A handle is not
+ *                thread-safe; use one handle per stream.
+ */
+#ifndef BBDG_H
+#define BBDG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BBDG_OK 0
+#define BBDG_E_ARG (-1)       /* null pointer, size or count out of range */
+#define BBDG_E_ORDER (-2)     /* N outside 1..9 */
+#define BBDG_E_MESH (-3)      /* bad vertex id, J <= 0, non-conforming or asymmetric connectivity */
+#define BBDG_E_NONFINITE (-4) /* NaN or Inf in geometry, wavespeed or time-step arguments */
+#define BBDG_E_DTYPE (-5)     /* unknown element type */
+#define BBDG_E_BC (-6)        /* unknown boundary condition */
+#define BBDG_E_DEVICE (-7)    /* HIP runtime error: device selection, allocation, copy */
+#define BBDG_E_LAUNCH (-8)    /* kernel launch failed */
+#define BBDG_E_MODE (-9)      /* unknown right-hand-side mode */
+
+enum { BBDG_F64 = 0, BBDG_F32 = 1 };
+
+/* Domain-boundary exterior states (face of an element with EToE = -1):
+ *   RIGID:            p+ = p-,  u+ = u- - 2 (n.u-) n   (wall with u.n = 0)
+ *   PRESSURE_RELEASE: p+ = -p-, u+ = u-                (the mirror condition of Section 2)
+ * with c+ = c- on the boundary. */
+enum { BBDG_BC_RIGID = 0, BBDG_BC_PRESSURE_RELEASE = 1 };
+
+/* What bbdg_rhs evaluates: the whole right-hand side, or only its volume
+ * (derivative) or surface (flux + lift) part. */
+enum { BBDG_RHS_FULL = 0, BBDG_RHS_VOLUME = 1, BBDG_RHS_SURFACE = 2 };
+
+typedef struct bbdg_solver bbdg_solver;
+
+/* Np for order N, or BBDG_E_ORDER. */
+int bbdg_np(int N);
+
+/* Fills alpha (host, Np x 4 int32, caller-allocated) with the multi-index
+ * (a0,a1,a2,a3) of every coefficient in storage order (Section 3.1 defines
+ * B_ijkl; the order is this library's). */
+int bbdg_alpha_table(int N, int32_t* alpha);
+
+/* Geometric factors and face connectivity of an affine tetrahedral mesh
+ * (Section 3: affine maps, geometric factors, Jacobians; faces are matched
+ * through their global vertex sets).  Inputs (host): VX (Nv x 3 double)
+ * vertex coordinates, EToV (K x 4 int32) vertex ids of each element.
+ * Outputs (host, caller-allocated): geo (K x 10), EToE, EToF, EToO (K x 4),
+ * in the layouts above.  Fails with BBDG_E_MESH on an out-of-range vertex id,
+ * J <= 0, or a face shared by more than two elements. */
+int bbdg_mesh_geometry(int64_t K, int64_t Nv, const double* VX, const int32_t* EToV,
+                       double* geo, int32_t* EToE, int8_t* EToF, int8_t* EToO);
+
+/* Creates a solver for order N, element type dtype (BBDG_F64 / BBDG_F32),
+ * K elements with the given connectivity (host), geometry (host, K x 10) and
+ * wavespeed c (host, K doubles, c > 0; rho = 1, kappa = c^2), boundary
+ * condition bc, on HIP device `device`.  Everything is validated first:
+ * connectivity must be symmetric (EToE[EToE[k][f]][EToF[k][f]] == k, with
+ * EToF of that entry equal to f and a consistent inverse orientation). */
+int bbdg_create(bbdg_solver** out, int N, int dtype, int64_t K,
+                const int32_t* EToE, const int8_t* EToF, const int8_t* EToO,
+                const double* geo, const double* c, int bc, int device);
+
+/* Order, element type and element count of a solver. */
+int bbdg_info(const bbdg_solver* s, int* N, int* dtype, int64_t* K, int* Np);
+
+/* One right-hand-side evaluation: rhs = A(q) (mode BBDG_RHS_FULL), or only
+ * its volume or surface part.  q and rhs are device (4, K, Np) arrays of the
+ * solver's element type; they must not overlap. */
+int bbdg_rhs(bbdg_solver* s, const void* q, void* rhs, int mode, void* stream);
+
+/* Bytes of device work space that bbdg_run needs: the LSRK residual and a
+ * second field buffer, 2 * 4 * K * Np elements. */
+size_t bbdg_work_bytes(const bbdg_solver* s);
+
+/* Advances q (device (4, K, Np), in/out) by `steps` LSRK4 steps of size dt
+ * from time t0.  work: device, >= bbdg_work_bytes(s), 256-byte aligned; its
+ * contents on entry are ignored.  steps >= 0, dt finite. */
+int bbdg_run(bbdg_solver* s, void* q, void* work, double t0, double dt, int64_t steps,
+             void* stream);
+
+/* Synchronises the solver's device and frees its tables.  Accepts NULL. */
+int bbdg_destroy(bbdg_solver* s);
+
+/* Static description of an error code. */
+const char* bbdg_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BBDG_H */

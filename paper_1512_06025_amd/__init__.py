@@ -1,0 +1,16 @@
+"""MI355X-native Bernstein-Bezier DG solver for the acoustic wave equation.
+
+The compute path is libbbdg.so (hand-written HIP kernels for gfx950 behind a
+C ABI, include/bbdg.h).  This package holds its build script, the ctypes
+binding and a thin torch-facing wrapper; PyTorch supplies device memory and
+streams only.
+"""
+from ._lib import (BBDG_BC_PRESSURE_RELEASE, BBDG_BC_RIGID, BBDG_F32, BBDG_F64,
+                   BBDG_RHS_FULL, BBDG_RHS_SURFACE, BBDG_RHS_VOLUME, BBDGError, load)
+from .solver import MeshData, Solver, alpha_table, mesh_geometry, np_count
+
+__all__ = [
+    "Solver", "MeshData", "alpha_table", "mesh_geometry", "np_count", "load", "BBDGError",
+    "BBDG_F64", "BBDG_F32", "BBDG_BC_RIGID", "BBDG_BC_PRESSURE_RELEASE",
+    "BBDG_RHS_FULL", "BBDG_RHS_VOLUME", "BBDG_RHS_SURFACE",
+]

@@ -1,0 +1,29 @@
+// Kernel argument blocks and launch entry points (host side of the kernels).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bbdg {
+
+// Arguments of the fused stage kernel.  In stage mode the kernel reads qin
+// (and res unless read_res == 0), writes res and qout; in right-hand-side
+// modes it reads qin and writes the right-hand side to qout.
+template <typename T>
+struct StageArgs {
+  const T* qin;
+  T* qout;
+  T* res;
+  const double* geo;      // K x kGeoStride
+  const int32_t* etoe;    // K x 4, -1 on the boundary
+  const uint8_t* etofo;   // K x 4: neighbour face | orientation << 2
+  const uint16_t* tab;    // index tables of the order
+  int64_t K;
+  T rk_a, rk_b, dt;
+  int read_res;
+  int bc;
+};
+
+template <typename T>
+hipError_t launch_stage(int N, int mode, const StageArgs<T>& a, hipStream_t stream);
+
+}  // namespace bbdg

@@ -1,0 +1,109 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Tolerances: relative L2 over all of q of 1e-12 in FP64 and 1e-5 in FP32.
+In FP32 runs the oracle starts from the same float32-rounded input.
+"""
+import numpy as np
+import pytest
+
+import workload
+from oracle import dg
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-12, "f32": 1e-5}
+
+
+def _rel(a, b):
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+def _setup(n, N, jitter=0.1, c=(1.0, 3.0), bc="rigid", drop_last=0):
+    import paper_1512_06025_amd as P
+    VX, EToV = workload.kuhn_cube_mesh(n, jitter, drop_last=drop_last)
+    cc = workload.wavespeed(EToV.shape[0], *c)
+    mesh = P.mesh_geometry(VX, EToV)
+    prob = dg.Problem(VX, EToV, N, cc, bc)
+    return P, mesh, cc, prob
+
+
+def _to_dev(x, dtype):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda", torch.float64 if dtype == "f64" else torch.float32)
+
+
+def _host(x):
+    torch.cuda.synchronize()
+    return x.detach().to("cpu", torch.float64).numpy()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("N", list(range(1, 10)))
+def test_rhs_parity(N, dtype):
+    # 2^3 cubes, 5 elements dropped: ragged element count, interior boundary faces
+    P, mesh, c, prob = _setup(2, N, drop_last=5)
+    q = workload.random_coeffs(prob.K, prob.Np)
+    if dtype == "f32":
+        q = q.astype(np.float32).astype(np.float64)
+    s = P.Solver(N, mesh, c, dtype=dtype)
+    qd = _to_dev(q, dtype)
+    for mode, kw in ((P.BBDG_RHS_VOLUME, dict(surface=False)),
+                     (P.BBDG_RHS_SURFACE, dict(volume=False)),
+                     (P.BBDG_RHS_FULL, {})):
+        got = _host(s.rhs(qd, mode))
+        want = prob.rhs(q, **kw)
+        err = _rel(got, want)
+        assert err < TOL[dtype], (N, dtype, mode, err)
+    s.close()
+
+
+@pytest.mark.parametrize("bc", ["rigid", "pressure_release"])
+def test_rhs_parity_boundary_conditions(bc):
+    P, mesh, c, prob = _setup(3, 4, bc=bc)
+    q = workload.random_coeffs(prob.K, prob.Np)
+    s = P.Solver(4, mesh, c, dtype="f64", bc=bc)
+    got = _host(s.rhs(_to_dev(q, "f64")))
+    assert _rel(got, prob.rhs(q)) < 1e-12
+    s.close()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_run_parity_c1(dtype):
+    """384 tets, N=3, c=1, standing mode, rigid walls, dt = 0.5 h/(N+1)^2, 10 steps."""
+    import paper_1512_06025_amd as P
+    cfg, VX, EToV, c = workload.build_preset("c1")
+    prob = dg.Problem(VX, EToV, cfg["N"], c)
+    q0 = dg.initial_state(prob, workload.standing_mode_p0)
+    if dtype == "f32":
+        q0 = q0.astype(np.float32).astype(np.float64)
+    want = prob.lsrk4(q0, cfg["dt"], cfg["steps"])
+    s = P.Solver(cfg["N"], P.mesh_geometry(VX, EToV), c, dtype=dtype)
+    qd = _to_dev(q0, dtype)
+    s.run(qd, cfg["dt"], cfg["steps"])
+    err = _rel(_host(qd), want)
+    assert err < TOL[dtype], err
+    s.close()
+
+
+@pytest.mark.parametrize("steps", [0, 1, 2, 3])
+def test_run_step_counts(steps):
+    """Odd and even stage counts (the ping-pong buffer ends in either place)."""
+    P, mesh, c, prob = _setup(2, 2, drop_last=1)
+    q = workload.random_coeffs(prob.K, prob.Np)
+    dt = 1e-3
+    s = P.Solver(2, mesh, c)
+    qd = _to_dev(q, "f64")
+    s.run(qd, dt, steps)
+    assert _rel(_host(qd), prob.lsrk4(q, dt, steps)) < 1e-12
+    s.close()
+
+
+def test_run_is_bitwise_repeatable():
+    P, mesh, c, prob = _setup(3, 5)
+    q = workload.random_coeffs(prob.K, prob.Np)
+    s = P.Solver(5, mesh, c)
+    a, b = _to_dev(q, "f64"), _to_dev(q, "f64")
+    s.run(a, 1e-3, 3)
+    s.run(b, 1e-3, 3)
+    assert torch.equal(a, b)
+    s.close()
