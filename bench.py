@@ -51,6 +51,28 @@ def time_gpu(P, torch, N, mesh, c, q0, dt, steps, warmup, dtype):
     return ms, finite
 
 
+def copy_probe(torch, P, nbytes=1 << 30, reps=20):
+    """Bandwidth of a plain streaming copy (read + write bytes per second)."""
+    from paper_1512_06025_amd import _lib
+    lib = _lib.load()
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    stream = torch.cuda.current_stream()
+    sp = _lib.ctypes.c_void_p(stream.cuda_stream)
+    _lib.check(lib.bbdg_copy_probe(src.data_ptr(), dst.data_ptr(), nbytes, sp), "bbdg_copy_probe")
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        lib.bbdg_copy_probe(src.data_ptr(), dst.data_ptr(), nbytes, sp)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    ok = bool(torch.equal(src, dst))
+    return {"bytes_moved": 2 * nbytes, "us": ms * 1e3, "GBs": 2 * nbytes / (ms * 1e-3) / 1e9, "ok": ok}
+
+
 def cpu_baseline(VX, EToV, c, N, q0, dt, sample_steps):
     from threadpoolctl import threadpool_info
 
@@ -81,6 +103,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=1)
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-copy-probe", action="store_true")
+    ap.add_argument("--copy-probe-only", action="store_true",
+                    help="only run the streaming-copy probe (counter calibration)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -94,6 +119,10 @@ def main():
     import paper_1512_06025_amd as P
     import workload
     from paper_1512_06025_amd import ic
+
+    if args.copy_probe_only:
+        print(json.dumps({"copy_probe": copy_probe(torch, P)}), flush=True)
+        return
 
     over = {} if args.order is None else {"N": args.order}
     cfg, VX, EToV, c = workload.build_preset(args.config, **over)
@@ -151,6 +180,10 @@ def main():
         a32 = algorithmic_bytes_per_element(N, 4) * K / (st32 * 1e-6) / 1e9
         out["fp32"] = {"value": dof * stages / (ms32 * 1e-3), "ms_per_step": ms32 / args.steps,
                        "stage_us": st32, "achieved_GBs": a32, "frac": a32 / HBM_PEAK_GBS, "finite": ok32}
+    if not args.no_copy_probe:
+        cp = copy_probe(torch, P)
+        out["roofline"]["copy_probe_GBs"] = cp["GBs"]
+        out["roofline"]["frac_of_copy_probe"] = achieved / cp["GBs"]
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(VX, EToV, c, N, q0, dt, args.cpu_sample_steps)
     print(json.dumps(out), flush=True)

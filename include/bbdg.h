@@ -134,6 +134,12 @@ size_t bbdg_work_bytes(const bbdg_solver* s);
 int bbdg_run(bbdg_solver* s, void* q, void* work, double t0, double dt, int64_t steps,
              void* stream);
 
+/* Measurement aid, not part of the method: copies `bytes` (a multiple of 16,
+ * both pointers 16-byte aligned, no overlap) from device buffer src to dst
+ * with a plain streaming kernel on the current device.  Used to measure the
+ * bandwidth a simple copy reaches and to calibrate hardware byte counters. */
+int bbdg_copy_probe(const void* src, void* dst, size_t bytes, void* stream);
+
 /* Synchronises the solver's device and frees its tables.  Accepts NULL. */
 int bbdg_destroy(bbdg_solver* s);
 

@@ -77,8 +77,12 @@ class Problem:
     # -- building blocks ---------------------------------------------------
     def gradient(self, x):
         """Physical gradient coefficients of a scalar field x (K, Np): (3, K, Np)."""
-        bary = np.einsum("inm,km->ikn", self.D, x)          # (4, K, Np): D^i x per element
-        return np.einsum("kid,ikn->dkn", self.geo.grad_lambda, bary)
+        out = np.zeros((3,) + x.shape)
+        for i in range(4):
+            bary = x @ self.D[i].T                             # D^i x on every element
+            for d in range(3):
+                out[d] += self.geo.grad_lambda[:, i, d, None] * bary
+        return out
 
     def traces(self, q):
         """Own and exterior traces on every face node: (4 fields, K, 4, Nfp) each."""

@@ -36,6 +36,7 @@ SIGNATURES = {
     "bbdg_work_bytes": (_c.c_size_t, [_c.c_void_p]),
     "bbdg_run": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_double, _c.c_double,
                             _c.c_int64, _c.c_void_p]),
+    "bbdg_copy_probe": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_size_t, _c.c_void_p]),
     "bbdg_destroy": (_c.c_int, [_c.c_void_p]),
     "bbdg_strerror": (_c.c_char_p, [_c.c_int]),
 }

@@ -24,8 +24,9 @@ constexpr int tri_row(int g2, int m) { return g2 * (m + 1) - g2 * (g2 - 1) / 2; 
 constexpr int level_off(int j, int N) { return np_of(N) - np_of(N - j); }
 
 // Device geometry per element (double): grad lambda_1, grad lambda_2,
-// grad lambda_3 (x,y,z each), then the wavespeed c.
-constexpr int kGeoStride = 10;
+// grad lambda_3 (x,y,z each), the wavespeed c, then the wavespeed across each
+// of the four faces (the element's own c on boundary faces).
+constexpr int kGeoStride = 14;
 
 // uint16 index tables of one order, one contiguous device buffer:
 //   alpha   [Np][4]      multi-index components

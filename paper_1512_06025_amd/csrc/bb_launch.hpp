@@ -26,4 +26,6 @@ struct StageArgs {
 template <typename T>
 hipError_t launch_stage(int N, int mode, const StageArgs<T>& a, hipStream_t stream);
 
+hipError_t launch_copy_probe(const void* src, void* dst, size_t bytes, hipStream_t stream);
+
 }  // namespace bbdg

@@ -1,31 +1,45 @@
 // Fused Bernstein-Bezier DG stage kernel for gfx950 (wave64).
 //
-// One 64-lane workgroup owns EPW consecutive elements (EPW = 64/Np for
-// Np <= 32, otherwise 1) and computes, for each of them:
-//   1. the element's coefficients of (p,u,v,w) staged in LDS ([node][field]);
-//   2. surface part 1: on every face node the exterior trace (neighbour's
-//      coinciding control point through the orientation table, or the mirror
-//      state), and the upwind flux (Section 2) pre-scaled so that
-//        rhs_p   += sum_f E_L^f L_0 sp^f,   sp = kappa/2 (tau_p |g| [[p]] - g.[[u]])
-//        rhs_u_i += sum_f g_i E_L^f L_0 su^f, su = 1/2 (tau_u g.[[u]]/|g| - [[p]])
-//      with g = Fscale_f n_f = -2 grad(lambda_f) (only two face vectors per
-//      face need lifting, because the velocity flux is a scalar times n);
-//   3. surface part 2: w_0 = L_0 s on the 8 face vectors (at most 7 nonzeros
-//      per row; L_0[b,b] = 1/2 sum_k (b_k+1)^2, L_0[b, b+e_k-e_m] = 1/2 (b_k+1) b_m,
-//      the entries of ((N+1)^2/2)(E^{N+1}_N)^T E^{N+1}_N, Section 3.1.2);
-//   4. surface part 3: E_L^f applied as N one-degree reductions
-//      w_j = (E^{N-j+1}_{N-j})^T w_{j-1},  [E^T w](b) = sum_k (b_k+1)/(m+1) w(b+e_k)
-//      (the slice-by-slice order of Algorithm 1), all levels kept in LDS; the
-//      volume node alpha then gathers ell_{alpha_f} w_{alpha_f}(alpha without f)
-//      from every face, ell_j = (-1)^j C(N,j)/(1+j);
-//   5. volume part (Algorithm 2 with the row form of Lemma 1, Appendix A.1):
-//      (D^i f)(alpha) = sum_j alpha_j f[alpha + e_i - e_j]; the physical
-//      gradient is sum_{i=1..3} grad(lambda_i) (D^i - D^0) f;
-//   6. the low-storage RK4 update res = a res + dt rhs, q_out = q + b res
-//      (fused; stage mode), or a plain store of the right-hand side.
-// The workgroup is a single wavefront, so its barriers are cheap and no
-// other wave waits on it.  Fields ping-pong between q_in and q_out, so a
-// stage never overwrites a trace that another workgroup still reads.
+// Work decomposition.  A workgroup holds WPB = 4 independent wavefronts.  Each
+// wavefront owns E consecutive elements at a time (E = 64/Np for Np <= 32,
+// otherwise 1) and loops over element groups (persistent grid).  The waves of
+// a workgroup share the order's index tables, loaded into LDS once; after
+// that a wave only synchronises with itself (LDS operations of a wavefront
+// complete in issue order, so an LDS-only fence plus a wave barrier orders
+// them while global loads stay in flight).  Consecutive workgroups land on
+// different XCDs, so the element range is split into 8 contiguous parts, one
+// per XCD, and each XCD's waves stride through their part: neighbouring
+// elements are processed by the same XCD at about the same time and their
+// face traces hit its L2.
+//
+// One latency round per element group: the group's connectivity/geometry
+// header was prefetched during the previous group; own coefficients, LSRK
+// residual and the neighbours' face traces are issued together, and the next
+// header is prefetched behind them.
+//
+// Per element:
+//   geometry, once: g_f = Fscale_f n_f = -2 grad(lambda_f), |g_f|, and the flux
+//     weights of face f (tau_p = 2/(c+c'), tau_u = (c+c')/2, rho = 1);
+//   volume (Algorithm 2, row form of Lemma 1 / Appendix A.1):
+//     (D^i f)(alpha) = sum_j alpha_j f[alpha + e_i - e_j],
+//     grad f = sum_{i=0..3} grad(lambda_i) D^i f;
+//     rhs_p = -kappa div u, rhs_u = -grad p;
+//   surface (Section 2 upwind flux, Section 3.1.2 factorisation L^f = E_L^f L_0):
+//     on face node g: sp = kappa/2 (tau_p |g_f| [[p]] - g_f.[[u]]),
+//                     su = 1/2 (tau_u g_f.[[u]]/|g_f| - [[p]]);
+//     w_0 = L_0 s:  L_0[b,b] = 1/2 sum_k (b_k+1)^2, L_0[b, b+e_k-e_m] = 1/2 (b_k+1) b_m
+//                   (the entries of ((N+1)^2/2) (E^{N+1}_N)^T E^{N+1}_N);
+//     w_j = (E^{N-j+1}_{N-j})^T w_{j-1}, [E^T w](b) = sum_k (b_k+1)/(m+1) w(b+e_k)
+//                   (the one-degree reductions of Algorithm 1);
+//     rhs_p(alpha) += sum_f ell_{alpha_f} w^f_p,alpha_f(alpha without f),
+//     rhs_u(alpha) += sum_f g_f ell_{alpha_f} w^f_u,alpha_f(alpha without f),
+//     ell_j = (-1)^j C(N,j)/(1+j).
+//   The rows of L_0 and of the reductions are spread over (vector, position)
+//   pairs, vector = lane mod 2*FB; their coefficients and input positions come
+//   from descriptor tables built in LDS once per workgroup.
+//   LSRK4 update (fused): res = a res + dt rhs, q_out = q + b res.
+// Fields ping-pong between q_in and q_out, so no stage overwrites a trace
+// that another wave still reads.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -34,278 +48,488 @@
 
 namespace bbdg {
 
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+template <int N, typename T>
+struct Shape {
+  static constexpr int Np = np_of(N);
+  static constexpr int Nfp = nfp_of(N);
+  static constexpr int E = (Np <= 32) ? (64 / Np) : 1;    // elements per wave group
+  static constexpr int NPL = (E * Np + 63) / 64;          // nodes per lane
+  static constexpr int NFI = (E * 4 * Nfp + 63) / 64;     // face items per lane
+  // faces per lift batch (bounds the LDS of the interleaved face vectors)
+  static constexpr int FB = sizeof(T) == 8 ? (N >= 8 ? 1 : (N >= 6 ? 2 : 4)) : (N >= 8 ? 2 : 4);
+  static constexpr int NV = 2 * FB;
+  static constexpr int WPB = 4;
+  static constexpr int HG = E * kGeoStride;               // header doubles per wave
+  static constexpr int NHG = (HG + 63) / 64;
+  static constexpr int NHE = (E * 4 + 63) / 64;
+  // per-element derived geometry (type T): grad lambda_0..3 (12), kappa, pad,
+  // then per face f at 16 + 8 f: g_x, g_y, g_z, a_p, a_u, b_u, pad, pad with
+  //   sp = a_p [[p]] - a_u g.[[u]],  su = b_u g.[[u]] - [[p]]/2.
+  static constexpr int GEO = 48;
+};
+
+// Occupancy target (waves per SIMD) that bounds the register allocation.
+template <int N, typename T>
+struct Occ {
+  static constexpr int f64[10] = {0, 3, 3, 4, 4, 4, 3, 2, 2, 2};
+  static constexpr int f32[10] = {0, 4, 4, 5, 5, 5, 4, 4, 3, 2};
+  static constexpr int value = sizeof(T) == 8 ? f64[N] : f32[N];
+};
+
 template <int N>
 struct Ell {
-  // ell_j = (-1)^j C(N,j)/(1+j), j = 0..N (Section 3.1.2)
   static constexpr double binom(int n, int k) {
     double r = 1.0;
     for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
     return r;
   }
+  // ell_j = (-1)^j C(N,j)/(1+j), j = 0..N (Section 3.1.2)
   static constexpr double value(int j) { return ((j & 1) ? -1.0 : 1.0) * binom(N, j) / (1.0 + j); }
 };
 
-template <int N>
-__device__ __forceinline__ double ell_of(int j) {
-  double r = 0.0;
+template <int N, typename T>
+struct Header {
+  double geo[Shape<N, T>::NHG];
+  int32_t etoe[Shape<N, T>::NHE];
+  uint32_t fo[Shape<N, T>::NHE];
+};
+
+template <int N, typename T>
+__device__ __forceinline__ void load_header(Header<N, T>& h, const StageArgs<T>& A, int64_t g, int lane) {
+  using S = Shape<N, T>;
+  const int64_t e0 = g * S::E;
 #pragma unroll
-  for (int i = 0; i <= N; ++i) r = (j == i) ? Ell<N>::value(i) : r;
-  return r;
+  for (int r = 0; r < S::NHG; ++r) {
+    const int v = lane + 64 * r;
+    int64_t idx = e0 * kGeoStride + v;
+    if (v >= S::HG || idx >= A.K * kGeoStride) idx = 0;
+    h.geo[r] = A.geo[idx];
+  }
+#pragma unroll
+  for (int r = 0; r < S::NHE; ++r) {
+    const int v = lane + 64 * r;
+    int64_t idx = e0 * 4 + v;
+    if (v >= S::E * 4 || idx >= A.K * 4) idx = 0;
+    h.etoe[r] = A.etoe[idx];
+    h.fo[r] = A.etofo[idx];
+  }
 }
 
 template <int N, typename T, int MODE>
-__global__ __launch_bounds__(64) void bb_stage_kernel(StageArgs<T> A) {
-  constexpr int Np = np_of(N);
-  constexpr int Nfp = nfp_of(N);
-  constexpr int EPW = (Np <= 32) ? (64 / Np) : 1;
-  constexpr int NPL = (EPW * Np + 63) / 64;
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Occ<N, T>::value)))
+void bb_stage_kernel(StageArgs<T> A) {
+  using S = Shape<N, T>;
+  constexpr int Np = S::Np, Nfp = S::Nfp, E = S::E, NPL = S::NPL, NFI = S::NFI;
+  constexpr int FB = S::FB, NV = S::NV, WPB = S::WPB, GEO = S::GEO;
   constexpr bool kVol = (MODE != kRhsSurface);
   constexpr bool kSurf = (MODE != kRhsVolume);
   constexpr TabLayout L = tab_layout(N);
 
-  __shared__ T sq[EPW][Np][4];
-  __shared__ T sflux[EPW][8][Nfp];
-  __shared__ T slev[EPW][8][Np];
+  // tables shared by the workgroup
+  __shared__ uint16_t t_nbr[24 * Nfp];
+  __shared__ uint16_t t_fnode[4 * Nfp];
+  __shared__ uint32_t t_alpha[Np];
+  __shared__ __attribute__((aligned(16))) uint16_t t_vnbr[Np][12];
+  __shared__ __attribute__((aligned(8))) uint16_t t_proj[Np][4];
+  __shared__ T t_ell[N + 1];
+  // L_0 rows: input positions (diagonal first) and weights; reduction rows:
+  // positions of b+e0 (b+e1 follows) and b+e2, and the weights (b_k+1)/(m+1)
+  __shared__ __attribute__((aligned(16))) uint8_t t_l0p[Nfp][8];
+  __shared__ __attribute__((aligned(16))) T t_l0c[Nfp][8];
+  __shared__ uint32_t t_lvp[Np];
+  __shared__ __attribute__((aligned(16))) T t_lvc[Np][4];
+  // per-wave buffers
+  __shared__ __attribute__((aligned(16))) T sq[WPB][E][Np][4];
+  __shared__ __attribute__((aligned(16))) T sfl[WPB][E][NV][Nfp];
+  __shared__ __attribute__((aligned(16))) T slev[WPB][E][NV][Np];
+  __shared__ __attribute__((aligned(16))) T sgeo[WPB][E][GEO];
+  __shared__ double shg[WPB][E * kGeoStride];
+  __shared__ int32_t she[WPB][E * 4];
+  __shared__ uint8_t shf[WPB][E * 4];
 
-  const int lane = threadIdx.x;
-  const int64_t e0 = (int64_t)blockIdx.x * EPW;
-  const int64_t K = A.K;
-  const int64_t KNp = K * Np;
-  const uint16_t* __restrict__ tab = A.tab;
-
-  // ---- 1. own coefficients -> registers and LDS ----------------------------
-  T qv[NPL][4];
+  const int tid = threadIdx.x;
+  for (int i = tid; i < 24 * Nfp; i += 64 * WPB) t_nbr[i] = A.tab[L.nbrnode + i];
+  for (int i = tid; i < 4 * Nfp; i += 64 * WPB) t_fnode[i] = A.tab[L.fnode + i];
+  for (int i = tid; i < Np; i += 64 * WPB) {
+    const uint16_t* a = A.tab + L.alpha + 4 * i;
+    t_alpha[i] = (uint32_t)a[0] | ((uint32_t)a[1] << 8) | ((uint32_t)a[2] << 16) | ((uint32_t)a[3] << 24);
 #pragma unroll
-  for (int r = 0; r < NPL; ++r) {
-    const int v = lane + 64 * r;
-    if (v < EPW * Np) {
-      const int el = v / Np;
-      const int n = v - el * Np;
-      const int64_t e = e0 + el;
+    for (int p = 0; p < 12; ++p) t_vnbr[i][p] = A.tab[L.vnbr + 12 * i + p];
 #pragma unroll
-      for (int f = 0; f < 4; ++f) {
-        T x = 0;
-        if (e < K) x = A.qin[f * KNp + e * Np + n];
-        qv[r][f] = x;
-        sq[el][n][f] = x;
-      }
+    for (int f = 0; f < 4; ++f) t_proj[i][f] = A.tab[L.proj + 4 * i + f];
+  }
+  if (tid <= N) {
+    double e = 0.0;
+#pragma unroll
+    for (int j = 0; j <= N; ++j) e = (tid == j) ? Ell<N>::value(j) : e;
+    t_ell[tid] = (T)e;
+  }
+  __syncthreads();
+  for (int gg = tid; gg < Nfp; gg += 64 * WPB) {
+    const uint32_t ap = t_alpha[gg];  // face-local (b0,b1,b2) = (a0,a1,a2) of node gg, a3 = 0
+    const int b0 = ap & 255, b1 = (ap >> 8) & 255, b2 = (ap >> 16) & 255;
+    const int row = tri_row(b2, N);
+    const int rdn = b2 >= 1 ? tri_row(b2 - 1, N) : 0;
+    const int rup = tri_row(b2 + 1, N);
+    // neighbours b + e_k - e_m with weights 1/2 (b_k+1) b_m (zero weight -> own position)
+    const int pos[6] = {row + b1 - 1, rup + b1 - 1, rdn + b1, rdn + b1 + 1, row + b1 + 1, rup + b1};
+    const int cw[6] = {(b0 + 1) * b1, (b2 + 1) * b1, (b0 + 1) * b2, (b1 + 1) * b2, (b1 + 1) * b0, (b2 + 1) * b0};
+    t_l0p[gg][0] = (uint8_t)gg;
+    t_l0c[gg][0] = (T)(0.5 * ((b0 + 1) * (b0 + 1) + (b1 + 1) * (b1 + 1) + (b2 + 1) * (b2 + 1)));
+    for (int q = 0; q < 6; ++q) {
+      t_l0p[gg][1 + q] = (uint8_t)(cw[q] ? pos[q] : gg);
+      t_l0c[gg][1 + q] = (T)(0.5 * cw[q]);
     }
+    t_l0p[gg][7] = (uint8_t)gg;
+    t_l0c[gg][7] = (T)0;
+  }
+  for (int nn = Nfp + tid; nn < Np; nn += 64 * WPB) {
+    // position nn of a face-layered vector = volume node nn seen from face 3
+    const uint32_t ap = t_alpha[nn];
+    const int b0 = ap & 255, b1 = (ap >> 8) & 255, b2 = (ap >> 16) & 255, j = ap >> 24;
+    const int m = N - j;
+    const int in0 = level_off(j - 1, N);
+    t_lvp[nn] = (uint32_t)(in0 + tri_row(b2, m + 1) + b1) | ((uint32_t)(in0 + tri_row(b2 + 1, m + 1) + b1) << 16);
+    t_lvc[nn][0] = (T)((double)(b0 + 1) / (m + 1));
+    t_lvc[nn][1] = (T)((double)(b1 + 1) / (m + 1));
+    t_lvc[nn][2] = (T)((double)(b2 + 1) / (m + 1));
+    t_lvc[nn][3] = (T)0;
   }
   __syncthreads();
 
-  if constexpr (kSurf) {
-    // ---- 2. traces and upwind flux ----------------------------------------
-    for (int v = lane; v < EPW * 4 * Nfp; v += 64) {
-      const int el = v / (4 * Nfp);
-      const int rem = v - el * 4 * Nfp;
-      const int f = rem / Nfp;
-      const int g = rem - f * Nfp;
-      const int64_t e = e0 + el;
-      T sp = 0, su = 0;
-      if (e < K) {
-        const int n = tab[L.fnode + f * Nfp + g];
-        const T pm = sq[el][n][0], um = sq[el][n][1], vm = sq[el][n][2], wm = sq[el][n][3];
-        const double* ge = A.geo + e * kGeoStride;
-        double gx, gy, gz;
-        if (f == 0) {
-          gx = 2.0 * (ge[0] + ge[3] + ge[6]);
-          gy = 2.0 * (ge[1] + ge[4] + ge[7]);
-          gz = 2.0 * (ge[2] + ge[5] + ge[8]);
-        } else {
-          gx = -2.0 * ge[3 * (f - 1) + 0];
-          gy = -2.0 * ge[3 * (f - 1) + 1];
-          gz = -2.0 * ge[3 * (f - 1) + 2];
-        }
-        const double gn = sqrt(gx * gx + gy * gy + gz * gz);
-        const double ce = ge[9];
-        const int32_t nb = A.etoe[e * 4 + f];
-        double cp = ce;
-        T jp, jgu;
-        const T tgx = (T)gx, tgy = (T)gy, tgz = (T)gz;
-        if (nb >= 0) {
-          const int info = A.etofo[e * 4 + f];
-          const int f2 = info & 3;
-          const int o = info >> 2;
-          const int n2 = tab[L.nbrnode + (f2 * 6 + o) * Nfp + g];
-          const int64_t off = (int64_t)nb * Np + n2;
-          const T pp = A.qin[off], up = A.qin[KNp + off], vp = A.qin[2 * KNp + off],
-                  wp = A.qin[3 * KNp + off];
-          cp = A.geo[(int64_t)nb * kGeoStride + 9];
-          jp = pp - pm;
-          jgu = tgx * (up - um) + tgy * (vp - vm) + tgz * (wp - wm);
-        } else if (A.bc == 0) {  // rigid wall mirror
-          jp = 0;
-          jgu = (T)(-2) * (tgx * um + tgy * vm + tgz * wm);
-        } else {  // pressure-release mirror
-          jp = (T)(-2) * pm;
-          jgu = 0;
-        }
-        const T tau_p = (T)(2.0 / (ce + cp));
-        const T tau_u = (T)(0.5 * (ce + cp));
-        const T kap = (T)(ce * ce);
-        sp = (T)0.5 * kap * (tau_p * (T)gn * jp - jgu);
-        su = (T)0.5 * (tau_u * jgu / (T)gn - jp);
-      }
-      sflux[el][f][g] = sp;
-      sflux[el][4 + f][g] = su;
-    }
-    __syncthreads();
+  const int lane0 = tid & 63;
+  const int w = tid >> 6;
+  const int64_t K = A.K;
+  const int64_t KNp = K * Np;
+  const int64_t G = (K + E - 1) / E;
+  // XCD-aware split of the element groups (gridDim.x is a multiple of 8)
+  const int xcd = blockIdx.x & 7;
+  const int64_t g_lo = G * xcd / 8, g_hi = G * (xcd + 1) / 8;
+  const int64_t wstride = (int64_t)(gridDim.x >> 3) * WPB;
+  int64_t g = g_lo + (int64_t)(blockIdx.x >> 3) * WPB + w;
 
-    // ---- 3. w_0 = L_0 s (level 0 of every face vector) ---------------------
-    for (int v = lane; v < EPW * 8 * Nfp; v += 64) {
-      const int el = v / (8 * Nfp);
-      const int rem = v - el * 8 * Nfp;
-      const int vec = rem / Nfp;
-      const int g = rem - vec * Nfp;
-      // face-local (b0,b1,b2) of position g = (a0,a1,a2) of volume node g (a3 = 0)
-      const int b0 = tab[L.alpha + 4 * g + 0];
-      const int b1 = tab[L.alpha + 4 * g + 1];
-      const int b2 = tab[L.alpha + 4 * g + 2];
-      const T* s = sflux[el][vec];
-      T acc = (T)(0.5 * ((b0 + 1) * (b0 + 1) + (b1 + 1) * (b1 + 1) + (b2 + 1) * (b2 + 1))) * s[g];
-      const int row = tri_row(b2, N);
-      if (b1 >= 1) {
-        acc += (T)(0.5 * (b0 + 1) * b1) * s[row + b1 - 1];                        // +e0 -e1
-        acc += (T)(0.5 * (b2 + 1) * b1) * s[tri_row(b2 + 1, N) + b1 - 1];         // +e2 -e1
-      }
-      if (b2 >= 1) {
-        acc += (T)(0.5 * (b0 + 1) * b2) * s[tri_row(b2 - 1, N) + b1];             // +e0 -e2
-        acc += (T)(0.5 * (b1 + 1) * b2) * s[tri_row(b2 - 1, N) + b1 + 1];         // +e1 -e2
-      }
-      if (b0 >= 1) {
-        acc += (T)(0.5 * (b1 + 1) * b0) * s[row + b1 + 1];                        // +e1 -e0
-        acc += (T)(0.5 * (b2 + 1) * b0) * s[tri_row(b2 + 1, N) + b1];            // +e2 -e0
-      }
-      slev[el][vec][g] = acc;
-    }
-    __syncthreads();
+  Header<N, T> hd;
+  if (g < g_hi) load_header<N, T>(hd, A, g, lane0);
 
-    // ---- 4. one-degree reductions, level j = 1..N ---------------------------
-#pragma unroll
-    for (int j = 1; j <= N; ++j) {
-      const int m = N - j;
-      const int out0 = level_off(j, N);
-      const int in0 = level_off(j - 1, N);
-      const int Tm = tri_of(m);
-      const T inv = (T)(1.0 / (m + 1));
-      for (int v = lane; v < EPW * 8 * Tm; v += 64) {
-        const int el = v / (8 * Tm);
-        const int rem = v - el * 8 * Tm;
-        const int vec = rem / Tm;
-        const int s = rem - vec * Tm;
-        // position out0 + s of the face-layered vector = volume node out0 + s seen from face 3
-        const int nn = out0 + s;
-        const int b0 = tab[L.alpha + 4 * nn + 0];
-        const int b1 = tab[L.alpha + 4 * nn + 1];
-        const int b2 = tab[L.alpha + 4 * nn + 2];
-        const T* w = slev[el][vec];
-        const int i0 = in0 + tri_row(b2, m + 1) + b1;       // b + e0
-        const int i2 = in0 + tri_row(b2 + 1, m + 1) + b1;   // b + e2
-        const T acc = (T)(b0 + 1) * w[i0] + (T)(b1 + 1) * w[i0 + 1] + (T)(b2 + 1) * w[i2];
-        slev[el][vec][nn] = acc * inv;
-      }
-      __syncthreads();
-    }
-  }
+  for (; g < g_hi; g += wstride) {
+    const int64_t e0 = g * E;
+    // Lane-derived addresses are cheap to recompute; hiding the lane id from
+    // loop-invariant code motion keeps them from being hoisted out of the
+    // element loop and occupying (or spilling) registers for its whole life.
+    int lane = lane0;
+    asm volatile("" : "+v"(lane));
 
-  // ---- 5./6. per node: volume term, lift gather, update --------------------
+    // ---- header of this group -> LDS --------------------------------------
+    wave_lds_sync();
 #pragma unroll
-  for (int r = 0; r < NPL; ++r) {
-    const int v = lane + 64 * r;
-    if (v >= EPW * Np) continue;
-    const int el = v / Np;
-    const int n = v - el * Np;
-    const int64_t e = e0 + el;
-    if (e >= K) continue;
-    const double* ge = A.geo + e * kGeoStride;
-    T gl[3][3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-      for (int d = 0; d < 3; ++d) gl[i][d] = (T)ge[3 * i + d];
-    const T kap = (T)(ge[9] * ge[9]);
-    int a[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) a[i] = tab[L.alpha + 4 * n + i];
-
-    T rhs[4] = {0, 0, 0, 0};
-    if constexpr (kVol) {
-      int nb[12];
-#pragma unroll
-      for (int p = 0; p < 12; ++p) nb[p] = tab[L.vnbr + 12 * n + p];
-      // pair index of (a, b): 3a + (b < a ? b : b - 1)
-      auto P = [&](int ai, int bi) { return nb[3 * ai + (bi < ai ? bi : bi - 1)]; };
-      T grad[4][3];
-#pragma unroll
-      for (int f = 0; f < 4; ++f) {
-        const T fc = sq[el][n][f];
-        T dl[3];
-#pragma unroll
-        for (int i = 1; i <= 3; ++i) {
-          T d = (T)a[0] * (sq[el][P(i, 0)][f] - fc) + (T)a[i] * (fc - sq[el][P(0, i)][f]);
-#pragma unroll
-          for (int m = 1; m <= 3; ++m) {
-            if (m == i) continue;
-            d += (T)a[m] * (sq[el][P(i, m)][f] - sq[el][P(0, m)][f]);
-          }
-          dl[i - 1] = d;
-        }
-#pragma unroll
-        for (int dd = 0; dd < 3; ++dd) grad[f][dd] = gl[0][dd] * dl[0] + gl[1][dd] * dl[1] + gl[2][dd] * dl[2];
-      }
-      rhs[0] = -kap * (grad[1][0] + grad[2][1] + grad[3][2]);
-      rhs[1] = -grad[0][0];
-      rhs[2] = -grad[0][1];
-      rhs[3] = -grad[0][2];
+    for (int r = 0; r < S::NHG; ++r) {
+      const int v = lane + 64 * r;
+      if (v < S::HG) shg[w][v] = hd.geo[r];
     }
+#pragma unroll
+    for (int r = 0; r < S::NHE; ++r) {
+      const int v = lane + 64 * r;
+      if (v < E * 4) {
+        she[w][v] = hd.etoe[r];
+        shf[w][v] = (uint8_t)hd.fo[r];
+      }
+    }
+    wave_lds_sync();
+
+    // ---- issue this group's loads: own q, residual, neighbour traces --------
+    T qv[NPL][4], rv[NPL][4];
+    int64_t noff[NPL];
+#pragma unroll
+    for (int r = 0; r < NPL; ++r) {
+      const int v = lane + 64 * r;
+      const int el = v / Np;
+      const int n = v - el * Np;
+      const bool ok = (v < E * Np) && (e0 + el < K);
+      noff[r] = ok ? (e0 + el) * Np + n : 0;
+#pragma unroll
+      for (int f = 0; f < 4; ++f) qv[r][f] = A.qin[f * KNp + noff[r]];
+      if (MODE == kStage && A.read_res) {
+#pragma unroll
+        for (int f = 0; f < 4; ++f) rv[r][f] = A.res[f * KNp + noff[r]];
+      } else {
+#pragma unroll
+        for (int f = 0; f < 4; ++f) rv[r][f] = 0;
+      }
+    }
+    T tr[NFI][4];
     if constexpr (kSurf) {
 #pragma unroll
-      for (int f = 0; f < 4; ++f) {
-        T gx, gy, gz;
-        if (f == 0) {
-          gx = (T)2 * (gl[0][0] + gl[1][0] + gl[2][0]);
-          gy = (T)2 * (gl[0][1] + gl[1][1] + gl[2][1]);
-          gz = (T)2 * (gl[0][2] + gl[1][2] + gl[2][2]);
-        } else {
-          gx = (T)(-2) * gl[f - 1][0];
-          gy = (T)(-2) * gl[f - 1][1];
-          gz = (T)(-2) * gl[f - 1][2];
+      for (int r = 0; r < NFI; ++r) {
+        const int v = lane + 64 * r;
+        const int el = v / (4 * Nfp);
+        const int rem = v - el * 4 * Nfp;
+        const int f = rem / Nfp;
+        const int gg = rem - f * Nfp;
+        int64_t off = 0;
+        if (v < E * 4 * Nfp && e0 + el < K) {
+          const int nb = she[w][el * 4 + f];
+          const int info = shf[w][el * 4 + f];
+          if (nb >= 0) off = (int64_t)nb * Np + t_nbr[((info & 3) * 6 + (info >> 2)) * Nfp + gg];
         }
-        const int pos = tab[L.proj + 4 * n + f];
-        const T ell = (T)ell_of<N>(a[f]);
-        const T lp = ell * slev[el][f][pos];
-        const T lu = ell * slev[el][4 + f][pos];
-        rhs[0] += lp;
-        rhs[1] += gx * lu;
-        rhs[2] += gy * lu;
-        rhs[3] += gz * lu;
+#pragma unroll
+        for (int fl = 0; fl < 4; ++fl) tr[r][fl] = A.qin[fl * KNp + off];
+      }
+    }
+    // ---- prefetch the next group's header -----------------------------------
+    if (g + wstride < g_hi) load_header<N, T>(hd, A, g + wstride, lane);
+
+    // ---- per-element derived geometry (one lane per element face) ------------
+    for (int v = lane; v < E * 4; v += 64) {
+      const int el = v >> 2;
+      const int f = v & 3;
+      const double* ge = shg[w] + el * kGeoStride;
+      double gx, gy, gz;  // grad lambda_f
+      if (f == 0) {
+        gx = -(ge[0] + ge[3] + ge[6]);
+        gy = -(ge[1] + ge[4] + ge[7]);
+        gz = -(ge[2] + ge[5] + ge[8]);
+      } else {
+        gx = ge[3 * (f - 1) + 0];
+        gy = ge[3 * (f - 1) + 1];
+        gz = ge[3 * (f - 1) + 2];
+      }
+      const double ce = ge[9], cp = ge[10 + f];
+      const double gn = 2.0 * sqrt(gx * gx + gy * gy + gz * gz);  // |g_f| = Fscale_f
+      const double kap = ce * ce;
+      T* o = sgeo[w][el];
+      o[3 * f + 0] = (T)gx;
+      o[3 * f + 1] = (T)gy;
+      o[3 * f + 2] = (T)gz;
+      if (f == 0) o[12] = (T)kap;
+      T* fr = o + 16 + 8 * f;
+      fr[0] = (T)(-2.0 * gx);
+      fr[1] = (T)(-2.0 * gy);
+      fr[2] = (T)(-2.0 * gz);
+      fr[3] = (T)(0.5 * kap * (2.0 / (ce + cp)) * gn);  // a_p = kappa tau_p |g| / 2
+      fr[4] = (T)(0.5 * kap);                           // a_u = kappa / 2
+      fr[5] = (T)(0.5 * (0.5 * (ce + cp)) / gn);         // b_u = tau_u / (2 |g|)
+    }
+
+    // ---- own coefficients -> LDS -----------------------------------------------
+#pragma unroll
+    for (int r = 0; r < NPL; ++r) {
+      const int v = lane + 64 * r;
+      if (v < E * Np) {
+        const int el = v / Np;
+        const int n = v - el * Np;
+#pragma unroll
+        for (int f = 0; f < 4; ++f) sq[w][el][n][f] = qv[r][f];
+      }
+    }
+    wave_lds_sync();
+
+    // ---- volume term ------------------------------------------------------------
+    T rhs[NPL][4];
+#pragma unroll
+    for (int r = 0; r < NPL; ++r) {
+#pragma unroll
+      for (int f = 0; f < 4; ++f) rhs[r][f] = 0;
+    }
+    if constexpr (kVol) {
+#pragma unroll
+      for (int r = 0; r < NPL; ++r) {
+        const int v = lane + 64 * r;
+        if (v >= E * Np) continue;
+        const int el = v / Np;
+        const int n = v - el * Np;
+        const uint32_t ap = t_alpha[n];
+        const T av[4] = {(T)(ap & 255), (T)((ap >> 8) & 255), (T)((ap >> 16) & 255), (T)(ap >> 24)};
+        int nb[12];
+#pragma unroll
+        for (int p = 0; p < 12; ++p) nb[p] = t_vnbr[n][p];
+        // neighbour alpha + e_a - e_b: pair index 3a + (b < a ? b : b - 1)
+        auto P = [&](int ai, int bi) { return nb[3 * ai + (bi < ai ? bi : bi - 1)]; };
+        const T* ge = sgeo[w][el];
+        T div = 0, gp[3] = {0, 0, 0};
+        // one field at a time: 13 coefficients live instead of 52
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+          const T fc = qv[r][f];
+          T Di[4];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            T d = av[i] * fc;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+              if (b == i) continue;
+              d += av[b] * sq[w][el][P(i, b)][f];
+            }
+            Di[i] = d;
+          }
+          if (f == 0) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d)
+              gp[d] = ge[d] * Di[0] + ge[3 + d] * Di[1] + ge[6 + d] * Di[2] + ge[9 + d] * Di[3];
+          } else {
+            div += ge[f - 1] * Di[0] + ge[3 + f - 1] * Di[1] + ge[6 + f - 1] * Di[2] + ge[9 + f - 1] * Di[3];
+          }
+          __builtin_amdgcn_sched_barrier(0);
+        }
+        rhs[r][0] = -ge[12] * div;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) rhs[r][1 + d] = -gp[d];
       }
     }
 
-    const int64_t off = e * Np + n;
-    if constexpr (MODE == kStage) {
+    // ---- surface term, FB faces at a time ------------------------------------------
+    if constexpr (kSurf) {
 #pragma unroll
-      for (int f = 0; f < 4; ++f) {
-        T rs = A.dt * rhs[f];
-        if (A.read_res) rs += A.rk_a * A.res[f * KNp + off];
-        A.res[f * KNp + off] = rs;
-        A.qout[f * KNp + off] = qv[r][f] + A.rk_b * rs;
+      for (int fb0 = 0; fb0 < 4; fb0 += FB) {
+        // flux on the face nodes of faces fb0 .. fb0+FB-1
+#pragma unroll
+        for (int r = 0; r < NFI; ++r) {
+          const int v = lane + 64 * r;
+          const int el = v / (4 * Nfp);
+          const int rem = v - el * 4 * Nfp;
+          const int f = rem / Nfp;
+          const int gg = rem - f * Nfp;
+          if (v >= E * 4 * Nfp || f < fb0 || f >= fb0 + FB) continue;
+          T sp = 0, su = 0;
+          if (e0 + el < K) {
+            const int n = t_fnode[f * Nfp + gg];
+            const T pm = sq[w][el][n][0], um = sq[w][el][n][1], vm = sq[w][el][n][2], wm = sq[w][el][n][3];
+            const T* fr = sgeo[w][el] + 16 + 8 * f;
+            const T gx = fr[0], gy = fr[1], gz = fr[2];
+            T jp, jgu;
+            if (she[w][el * 4 + f] >= 0) {
+              jp = tr[r][0] - pm;
+              jgu = gx * (tr[r][1] - um) + gy * (tr[r][2] - vm) + gz * (tr[r][3] - wm);
+            } else if (A.bc == 0) {  // rigid wall mirror
+              jp = 0;
+              jgu = (T)(-2) * (gx * um + gy * vm + gz * wm);
+            } else {  // pressure-release mirror
+              jp = (T)(-2) * pm;
+              jgu = 0;
+            }
+            sp = fr[3] * jp - fr[4] * jgu;
+            su = fr[5] * jgu - (T)0.5 * jp;
+          }
+          sfl[w][el][f - fb0][gg] = sp;
+          sfl[w][el][FB + f - fb0][gg] = su;
+        }
+        wave_lds_sync();
+
+        // w_0 = L_0 s, one row per (vector, position) item
+        for (int v = lane; v < E * NV * Nfp; v += 64) {
+          const int vec = v % NV;
+          const int rest = v / NV;
+          const int el = rest / Nfp;
+          const int gg = rest - el * Nfp;
+          const T* sv = sfl[w][el][vec];
+          const uint2 pp = *reinterpret_cast<const uint2*>(t_l0p[gg]);
+          const T* c = t_l0c[gg];
+          T acc = c[0] * sv[gg];
+          acc += c[1] * sv[(pp.x >> 8) & 255];
+          acc += c[2] * sv[(pp.x >> 16) & 255];
+          acc += c[3] * sv[pp.x >> 24];
+          acc += c[4] * sv[pp.y & 255];
+          acc += c[5] * sv[(pp.y >> 8) & 255];
+          acc += c[6] * sv[(pp.y >> 16) & 255];
+          slev[w][el][vec][gg] = acc;
+        }
+        wave_lds_sync();
+
+        // one-degree reductions, level j = 1..N, one row per (vector, position) item
+#pragma unroll
+        for (int j = 1; j <= N; ++j) {
+          const int out0 = level_off(j, N);
+          const int Tm = tri_of(N - j);
+          for (int v = lane; v < E * NV * Tm; v += 64) {
+            const int vec = v % NV;
+            const int rest = v / NV;
+            const int el = rest / Tm;
+            const int nn = out0 + rest - el * Tm;
+            T* wv = slev[w][el][vec];
+            const uint32_t ip = t_lvp[nn];
+            const int i0 = ip & 0xffff, i2 = ip >> 16;
+            const T* c = t_lvc[nn];
+            wv[nn] = c[0] * wv[i0] + c[1] * wv[i0 + 1] + c[2] * wv[i2];
+          }
+          wave_lds_sync();
+        }
+
+        // gather the lifted values of this batch into the nodes
+#pragma unroll
+        for (int r = 0; r < NPL; ++r) {
+          const int v = lane + 64 * r;
+          if (v >= E * Np) continue;
+          const int el = v / Np;
+          const int n = v - el * Np;
+          const uint32_t ap = t_alpha[n];
+#pragma unroll
+          for (int fl = 0; fl < FB; ++fl) {
+            const int f = fb0 + fl;
+            const T* fr = sgeo[w][el] + 16 + 8 * f;
+            const int af = (ap >> (8 * f)) & 255;
+            const int pos = t_proj[n][f];
+            const T ell = t_ell[af];
+            const T lp = ell * slev[w][el][fl][pos];
+            const T lu = ell * slev[w][el][FB + fl][pos];
+            rhs[r][0] += lp;
+            rhs[r][1] += fr[0] * lu;
+            rhs[r][2] += fr[1] * lu;
+            rhs[r][3] += fr[2] * lu;
+          }
+        }
+        if (FB < 4) wave_lds_sync();
       }
-    } else {
+    }
+
+    // ---- update / store -------------------------------------------------------------
 #pragma unroll
-      for (int f = 0; f < 4; ++f) A.qout[f * KNp + off] = rhs[f];
+    for (int r = 0; r < NPL; ++r) {
+      const int v = lane + 64 * r;
+      const int el = v / Np;
+      if (v >= E * Np || e0 + el >= K) continue;
+      const int64_t off = noff[r];
+      if constexpr (MODE == kStage) {
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+          const T rs = A.dt * rhs[r][f] + A.rk_a * rv[r][f];
+          A.res[f * KNp + off] = rs;
+          A.qout[f * KNp + off] = qv[r][f] + A.rk_b * rs;
+        }
+      } else {
+#pragma unroll
+        for (int f = 0; f < 4; ++f) A.qout[f * KNp + off] = rhs[r][f];
+      }
     }
   }
 }
 
 template <int N, typename T, int MODE>
 static hipError_t launch_one(const StageArgs<T>& a, hipStream_t stream) {
-  constexpr int Np = np_of(N);
-  constexpr int EPW = (Np <= 32) ? (64 / Np) : 1;
-  const int64_t groups = (a.K + EPW - 1) / EPW;
+  using S = Shape<N, T>;
+  const int64_t groups = (a.K + S::E - 1) / S::E;
   if (groups <= 0) return hipSuccess;
-  if (groups > 0x7fffffffLL) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((bb_stage_kernel<N, T, MODE>), dim3((unsigned)groups), dim3(64), 0, stream, a);
+  static int resident = 0;  // co-resident workgroups per CU for this instantiation
+  static int cus = 0;
+  if (resident == 0) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return hipErrorInvalidDevice;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return hipErrorInvalidDevice;
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, bb_stage_kernel<N, T, MODE>, 64 * S::WPB, 0) != hipSuccess)
+      return hipErrorInvalidValue;
+    resident = occ > 0 ? occ : 1;
+  }
+  const int64_t needed = (groups + S::WPB - 1) / S::WPB;
+  int64_t grid = (int64_t)resident * cus;
+  if (grid > ((needed + 7) / 8) * 8) grid = ((needed + 7) / 8) * 8;
+  grid = ((grid + 7) / 8) * 8;
+  if (grid < 8) grid = 8;
+  hipLaunchKernelGGL((bb_stage_kernel<N, T, MODE>), dim3((unsigned)grid), dim3(64 * S::WPB), 0, stream, a);
   return hipGetLastError();
 }
 

@@ -19,7 +19,7 @@ using namespace bbdg;
 struct bbdg_solver {
   int N = 0, dtype = 0, bc = 0, device = 0;
   int64_t K = 0;
-  double* d_geo = nullptr;     // K x kGeoStride
+  double* d_geo = nullptr;     // K x kGeoStride: grad lambda_1..3, c, c across faces
   int32_t* d_etoe = nullptr;   // K x 4
   uint8_t* d_etofo = nullptr;  // K x 4
   uint16_t* d_tab = nullptr;   // tab_layout(N).size
@@ -342,6 +342,7 @@ int bbdg_create(bbdg_solver** out, int N, int dtype, int64_t K, const int32_t* E
     for (int f = 0; f < 4; ++f) {
       const int64_t slot = 4 * k + f;
       fo[(size_t)slot] = EToE[slot] >= 0 ? (uint8_t)((EToF[slot] & 3) | (EToO[slot] << 2)) : 0;
+      dgeo[(size_t)(kGeoStride * k + 10 + f)] = EToE[slot] >= 0 ? c[EToE[slot]] : c[k];
     }
   }
   const std::vector<uint16_t> tab = build_tables(N);
@@ -417,6 +418,15 @@ int bbdg_run(bbdg_solver* s, void* q, void* work, double t0, double dt, int64_t 
   hipStream_t st = (hipStream_t)stream;
   if (s->dtype == BBDG_F64) return run_typed<double>(s, (double*)q, (double*)work, dt, steps, st);
   return run_typed<float>(s, (float*)q, (float*)work, dt, steps, st);
+}
+
+int bbdg_copy_probe(const void* src, void* dst, size_t bytes, void* stream) {
+  if (!src || !dst || bytes % 16 != 0) return BBDG_E_ARG;
+  const char* a = (const char*)src;
+  const char* b = (const char*)dst;
+  if (a < b + bytes && b < a + bytes) return BBDG_E_ARG;
+  if (((uintptr_t)src) % 16 != 0 || ((uintptr_t)dst) % 16 != 0) return BBDG_E_ARG;
+  return launch_copy_probe(src, dst, bytes, (hipStream_t)stream) == hipSuccess ? BBDG_OK : BBDG_E_LAUNCH;
 }
 
 int bbdg_destroy(bbdg_solver* s) {
