@@ -109,7 +109,8 @@ int bbdg_mesh_geometry(int64_t K, int64_t Nv, const double* VX, const int32_t* E
 /* Creates a solver for order N, element type dtype (BBDG_F64 / BBDG_F32),
  * K elements with the given connectivity (host), geometry (host, K x 10) and
  * wavespeed c (host, K doubles, c > 0; rho = 1, kappa = c^2), boundary
- * condition bc, on HIP device `device`.  Everything is validated first:
+ * condition bc, on HIP device `device`; 4 K Np must stay below 2^31 (fields
+ * are addressed with 32-bit offsets).  Everything is validated first:
  * connectivity must be symmetric (EToE[EToE[k][f]][EToF[k][f]] == k, with
  * EToF of that entry equal to f and a consistent inverse orientation). */
 int bbdg_create(bbdg_solver** out, int N, int dtype, int64_t K,

@@ -24,9 +24,14 @@ constexpr int tri_row(int g2, int m) { return g2 * (m + 1) - g2 * (g2 - 1) / 2; 
 constexpr int level_off(int j, int N) { return np_of(N) - np_of(N - j); }
 
 // Device geometry per element (double): grad lambda_1, grad lambda_2,
-// grad lambda_3 (x,y,z each), the wavespeed c, then the wavespeed across each
-// of the four faces (the element's own c on boundary faces).
-constexpr int kGeoStride = 14;
+// grad lambda_3 (x,y,z each), kappa = c^2, then for each face f the upwind
+// flux weights a_p = kappa |g_f| / (c + c_f) and b_u = (c + c_f) / (4 |g_f|),
+// where g_f = -2 grad(lambda_f) and c_f is the wavespeed across face f (the
+// element's own c on boundary faces).
+constexpr int kGeoStride = 18;
+
+// Field arrays are addressed with 32-bit element offsets: 4 K Np < 2^31.
+constexpr int64_t kMaxFieldElems = (int64_t)1 << 31;
 
 // uint16 index tables of one order, one contiguous device buffer:
 //   alpha   [Np][4]      multi-index components

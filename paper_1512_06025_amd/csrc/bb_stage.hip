@@ -61,7 +61,7 @@ struct Shape {
   static constexpr int E = (Np <= 32) ? (64 / Np) : 1;    // elements per wave group
   static constexpr int NPL = (E * Np + 63) / 64;          // nodes per lane
   static constexpr int NFI = (E * 4 * Nfp + 63) / 64;     // face items per lane
-  // faces per lift batch (bounds the LDS of the interleaved face vectors)
+  // faces per lift batch (bounds the LDS of the face vectors)
   static constexpr int FB = sizeof(T) == 8 ? (N >= 8 ? 1 : (N >= 6 ? 2 : 4)) : (N >= 8 ? 2 : 4);
   static constexpr int NV = 2 * FB;
   static constexpr int WPB = 4;
@@ -121,6 +121,18 @@ __device__ __forceinline__ void load_header(Header<N, T>& h, const StageArgs<T>&
   }
 }
 
+// Element-offset access with a 32-bit byte offset (4 K Np < 2^31 is enforced
+// at create time), so loads and stores use a scalar base plus a 32-bit
+// vector offset.
+template <typename T>
+__device__ __forceinline__ T ld(const T* base, uint32_t idx) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + (idx * (uint32_t)sizeof(T)));
+}
+template <typename T>
+__device__ __forceinline__ void st(T* base, uint32_t idx, T x) {
+  *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + (idx * (uint32_t)sizeof(T))) = x;
+}
+
 template <int N, typename T, int MODE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Occ<N, T>::value)))
 void bb_stage_kernel(StageArgs<T> A) {
@@ -141,11 +153,11 @@ void bb_stage_kernel(StageArgs<T> A) {
   // L_0 rows: input positions (diagonal first) and weights; reduction rows:
   // positions of b+e0 (b+e1 follows) and b+e2, and the weights (b_k+1)/(m+1)
   __shared__ __attribute__((aligned(16))) uint8_t t_l0p[Nfp][8];
-  __shared__ __attribute__((aligned(16))) T t_l0c[Nfp][8];
+  __shared__ T t_l0c[7][Nfp];
   __shared__ uint32_t t_lvp[Np];
-  __shared__ __attribute__((aligned(16))) T t_lvc[Np][4];
+  __shared__ T t_lvc[3][Np];
   // per-wave buffers
-  __shared__ __attribute__((aligned(16))) T sq[WPB][E][Np][4];
+  __shared__ __attribute__((aligned(16))) T sq[WPB][E][4][Np];
   __shared__ __attribute__((aligned(16))) T sfl[WPB][E][NV][Nfp];
   __shared__ __attribute__((aligned(16))) T slev[WPB][E][NV][Np];
   __shared__ __attribute__((aligned(16))) T sgeo[WPB][E][GEO];
@@ -181,13 +193,12 @@ void bb_stage_kernel(StageArgs<T> A) {
     const int pos[6] = {row + b1 - 1, rup + b1 - 1, rdn + b1, rdn + b1 + 1, row + b1 + 1, rup + b1};
     const int cw[6] = {(b0 + 1) * b1, (b2 + 1) * b1, (b0 + 1) * b2, (b1 + 1) * b2, (b1 + 1) * b0, (b2 + 1) * b0};
     t_l0p[gg][0] = (uint8_t)gg;
-    t_l0c[gg][0] = (T)(0.5 * ((b0 + 1) * (b0 + 1) + (b1 + 1) * (b1 + 1) + (b2 + 1) * (b2 + 1)));
+    t_l0c[0][gg] = (T)(0.5 * ((b0 + 1) * (b0 + 1) + (b1 + 1) * (b1 + 1) + (b2 + 1) * (b2 + 1)));
     for (int q = 0; q < 6; ++q) {
       t_l0p[gg][1 + q] = (uint8_t)(cw[q] ? pos[q] : gg);
-      t_l0c[gg][1 + q] = (T)(0.5 * cw[q]);
+      t_l0c[1 + q][gg] = (T)(0.5 * cw[q]);
     }
     t_l0p[gg][7] = (uint8_t)gg;
-    t_l0c[gg][7] = (T)0;
   }
   for (int nn = Nfp + tid; nn < Np; nn += 64 * WPB) {
     // position nn of a face-layered vector = volume node nn seen from face 3
@@ -196,10 +207,9 @@ void bb_stage_kernel(StageArgs<T> A) {
     const int m = N - j;
     const int in0 = level_off(j - 1, N);
     t_lvp[nn] = (uint32_t)(in0 + tri_row(b2, m + 1) + b1) | ((uint32_t)(in0 + tri_row(b2 + 1, m + 1) + b1) << 16);
-    t_lvc[nn][0] = (T)((double)(b0 + 1) / (m + 1));
-    t_lvc[nn][1] = (T)((double)(b1 + 1) / (m + 1));
-    t_lvc[nn][2] = (T)((double)(b2 + 1) / (m + 1));
-    t_lvc[nn][3] = (T)0;
+    t_lvc[0][nn] = (T)((double)(b0 + 1) / (m + 1));
+    t_lvc[1][nn] = (T)((double)(b1 + 1) / (m + 1));
+    t_lvc[2][nn] = (T)((double)(b2 + 1) / (m + 1));
   }
   __syncthreads();
 
@@ -207,6 +217,7 @@ void bb_stage_kernel(StageArgs<T> A) {
   const int w = tid >> 6;
   const int64_t K = A.K;
   const int64_t KNp = K * Np;
+  const T* qin_f[4] = {A.qin, A.qin + KNp, A.qin + 2 * KNp, A.qin + 3 * KNp};
   const int64_t G = (K + E - 1) / E;
   // XCD-aware split of the element groups (gridDim.x is a multiple of 8)
   const int xcd = blockIdx.x & 7;
@@ -244,19 +255,19 @@ void bb_stage_kernel(StageArgs<T> A) {
 
     // ---- issue this group's loads: own q, residual, neighbour traces --------
     T qv[NPL][4], rv[NPL][4];
-    int64_t noff[NPL];
+    uint32_t noff[NPL];
 #pragma unroll
     for (int r = 0; r < NPL; ++r) {
       const int v = lane + 64 * r;
       const int el = v / Np;
       const int n = v - el * Np;
       const bool ok = (v < E * Np) && (e0 + el < K);
-      noff[r] = ok ? (e0 + el) * Np + n : 0;
+      noff[r] = ok ? (uint32_t)((e0 + el) * Np + n) : 0u;
 #pragma unroll
-      for (int f = 0; f < 4; ++f) qv[r][f] = A.qin[f * KNp + noff[r]];
+      for (int f = 0; f < 4; ++f) qv[r][f] = ld(qin_f[f], noff[r]);
       if (MODE == kStage && A.read_res) {
 #pragma unroll
-        for (int f = 0; f < 4; ++f) rv[r][f] = A.res[f * KNp + noff[r]];
+        for (int f = 0; f < 4; ++f) rv[r][f] = ld(A.res + f * KNp, noff[r]);
       } else {
 #pragma unroll
         for (int f = 0; f < 4; ++f) rv[r][f] = 0;
@@ -271,14 +282,14 @@ void bb_stage_kernel(StageArgs<T> A) {
         const int rem = v - el * 4 * Nfp;
         const int f = rem / Nfp;
         const int gg = rem - f * Nfp;
-        int64_t off = 0;
+        uint32_t off = 0;
         if (v < E * 4 * Nfp && e0 + el < K) {
           const int nb = she[w][el * 4 + f];
           const int info = shf[w][el * 4 + f];
-          if (nb >= 0) off = (int64_t)nb * Np + t_nbr[((info & 3) * 6 + (info >> 2)) * Nfp + gg];
+          if (nb >= 0) off = (uint32_t)nb * Np + t_nbr[((info & 3) * 6 + (info >> 2)) * Nfp + gg];
         }
 #pragma unroll
-        for (int fl = 0; fl < 4; ++fl) tr[r][fl] = A.qin[fl * KNp + off];
+        for (int fl = 0; fl < 4; ++fl) tr[r][fl] = ld(qin_f[fl], off);
       }
     }
     // ---- prefetch the next group's header -----------------------------------
@@ -299,21 +310,18 @@ void bb_stage_kernel(StageArgs<T> A) {
         gy = ge[3 * (f - 1) + 1];
         gz = ge[3 * (f - 1) + 2];
       }
-      const double ce = ge[9], cp = ge[10 + f];
-      const double gn = 2.0 * sqrt(gx * gx + gy * gy + gz * gz);  // |g_f| = Fscale_f
-      const double kap = ce * ce;
       T* o = sgeo[w][el];
       o[3 * f + 0] = (T)gx;
       o[3 * f + 1] = (T)gy;
       o[3 * f + 2] = (T)gz;
-      if (f == 0) o[12] = (T)kap;
+      if (f == 0) o[12] = (T)ge[9];
       T* fr = o + 16 + 8 * f;
       fr[0] = (T)(-2.0 * gx);
       fr[1] = (T)(-2.0 * gy);
       fr[2] = (T)(-2.0 * gz);
-      fr[3] = (T)(0.5 * kap * (2.0 / (ce + cp)) * gn);  // a_p = kappa tau_p |g| / 2
-      fr[4] = (T)(0.5 * kap);                           // a_u = kappa / 2
-      fr[5] = (T)(0.5 * (0.5 * (ce + cp)) / gn);         // b_u = tau_u / (2 |g|)
+      fr[3] = (T)ge[10 + f];     // a_p
+      fr[4] = (T)(0.5 * ge[9]);  // a_u = kappa / 2
+      fr[5] = (T)ge[14 + f];     // b_u
     }
 
     // ---- own coefficients -> LDS -----------------------------------------------
@@ -324,7 +332,7 @@ void bb_stage_kernel(StageArgs<T> A) {
         const int el = v / Np;
         const int n = v - el * Np;
 #pragma unroll
-        for (int f = 0; f < 4; ++f) sq[w][el][n][f] = qv[r][f];
+        for (int f = 0; f < 4; ++f) sq[w][el][f][n] = qv[r][f];
       }
     }
     wave_lds_sync();
@@ -363,7 +371,7 @@ void bb_stage_kernel(StageArgs<T> A) {
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
               if (b == i) continue;
-              d += av[b] * sq[w][el][P(i, b)][f];
+              d += av[b] * sq[w][el][f][P(i, b)];
             }
             Di[i] = d;
           }
@@ -398,7 +406,7 @@ void bb_stage_kernel(StageArgs<T> A) {
           T sp = 0, su = 0;
           if (e0 + el < K) {
             const int n = t_fnode[f * Nfp + gg];
-            const T pm = sq[w][el][n][0], um = sq[w][el][n][1], vm = sq[w][el][n][2], wm = sq[w][el][n][3];
+            const T pm = sq[w][el][0][n], um = sq[w][el][1][n], vm = sq[w][el][2][n], wm = sq[w][el][3][n];
             const T* fr = sgeo[w][el] + 16 + 8 * f;
             const T gx = fr[0], gy = fr[1], gz = fr[2];
             T jp, jgu;
@@ -420,22 +428,21 @@ void bb_stage_kernel(StageArgs<T> A) {
         }
         wave_lds_sync();
 
-        // w_0 = L_0 s, one row per (vector, position) item
+        // w_0 = L_0 s, one row per (vector, position) item, position fastest
         for (int v = lane; v < E * NV * Nfp; v += 64) {
-          const int vec = v % NV;
-          const int rest = v / NV;
-          const int el = rest / Nfp;
-          const int gg = rest - el * Nfp;
+          const int gg = v % Nfp;
+          const int rest = v / Nfp;
+          const int vec = rest % NV;
+          const int el = rest / NV;
           const T* sv = sfl[w][el][vec];
           const uint2 pp = *reinterpret_cast<const uint2*>(t_l0p[gg]);
-          const T* c = t_l0c[gg];
-          T acc = c[0] * sv[gg];
-          acc += c[1] * sv[(pp.x >> 8) & 255];
-          acc += c[2] * sv[(pp.x >> 16) & 255];
-          acc += c[3] * sv[pp.x >> 24];
-          acc += c[4] * sv[pp.y & 255];
-          acc += c[5] * sv[(pp.y >> 8) & 255];
-          acc += c[6] * sv[(pp.y >> 16) & 255];
+          T acc = t_l0c[0][gg] * sv[gg];
+          acc += t_l0c[1][gg] * sv[(pp.x >> 8) & 255];
+          acc += t_l0c[2][gg] * sv[(pp.x >> 16) & 255];
+          acc += t_l0c[3][gg] * sv[pp.x >> 24];
+          acc += t_l0c[4][gg] * sv[pp.y & 255];
+          acc += t_l0c[5][gg] * sv[(pp.y >> 8) & 255];
+          acc += t_l0c[6][gg] * sv[(pp.y >> 16) & 255];
           slev[w][el][vec][gg] = acc;
         }
         wave_lds_sync();
@@ -446,15 +453,15 @@ void bb_stage_kernel(StageArgs<T> A) {
           const int out0 = level_off(j, N);
           const int Tm = tri_of(N - j);
           for (int v = lane; v < E * NV * Tm; v += 64) {
-            const int vec = v % NV;
-            const int rest = v / NV;
-            const int el = rest / Tm;
-            const int nn = out0 + rest - el * Tm;
+            const int s = v % Tm;
+            const int rest = v / Tm;
+            const int vec = rest % NV;
+            const int el = rest / NV;
+            const int nn = out0 + s;
             T* wv = slev[w][el][vec];
             const uint32_t ip = t_lvp[nn];
             const int i0 = ip & 0xffff, i2 = ip >> 16;
-            const T* c = t_lvc[nn];
-            wv[nn] = c[0] * wv[i0] + c[1] * wv[i0 + 1] + c[2] * wv[i2];
+            wv[nn] = t_lvc[0][nn] * wv[i0] + t_lvc[1][nn] * wv[i0 + 1] + t_lvc[2][nn] * wv[i2];
           }
           wave_lds_sync();
         }
@@ -492,17 +499,17 @@ void bb_stage_kernel(StageArgs<T> A) {
       const int v = lane + 64 * r;
       const int el = v / Np;
       if (v >= E * Np || e0 + el >= K) continue;
-      const int64_t off = noff[r];
+      const uint32_t off = noff[r];
       if constexpr (MODE == kStage) {
 #pragma unroll
         for (int f = 0; f < 4; ++f) {
           const T rs = A.dt * rhs[r][f] + A.rk_a * rv[r][f];
-          A.res[f * KNp + off] = rs;
-          A.qout[f * KNp + off] = qv[r][f] + A.rk_b * rs;
+          st(A.res + f * KNp, off, rs);
+          st(A.qout + f * KNp, off, qv[r][f] + A.rk_b * rs);
         }
       } else {
 #pragma unroll
-        for (int f = 0; f < 4; ++f) A.qout[f * KNp + off] = rhs[r][f];
+        for (int f = 0; f < 4; ++f) st(A.qout + f * KNp, off, rhs[r][f]);
       }
     }
   }

@@ -19,7 +19,7 @@ using namespace bbdg;
 struct bbdg_solver {
   int N = 0, dtype = 0, bc = 0, device = 0;
   int64_t K = 0;
-  double* d_geo = nullptr;     // K x kGeoStride: grad lambda_1..3, c, c across faces
+  double* d_geo = nullptr;     // K x kGeoStride (see bb_common.hpp)
   int32_t* d_etoe = nullptr;   // K x 4
   uint8_t* d_etofo = nullptr;  // K x 4
   uint16_t* d_tab = nullptr;   // tab_layout(N).size
@@ -309,6 +309,7 @@ int bbdg_create(bbdg_solver** out, int N, int dtype, int64_t K, const int32_t* E
   if (bc != BBDG_BC_RIGID && bc != BBDG_BC_PRESSURE_RELEASE) return BBDG_E_BC;
   if (K <= 0 || K > (int64_t)0x7ffffffe || !EToE || !EToF || !EToO || !geo || !c || device < 0)
     return BBDG_E_ARG;
+  if (4 * K * (int64_t)np_of(N) >= kMaxFieldElems) return BBDG_E_ARG;
   if (!finite_all(geo, 10 * K) || !finite_all(c, K)) return BBDG_E_NONFINITE;
   for (int64_t k = 0; k < K; ++k) {
     if (!(geo[10 * k + 9] > 0.0)) return BBDG_E_MESH;
@@ -337,12 +338,20 @@ int bbdg_create(bbdg_solver** out, int N, int dtype, int64_t K, const int32_t* E
   std::vector<double> dgeo((size_t)(kGeoStride * K));
   std::vector<uint8_t> fo((size_t)(4 * K));
   for (int64_t k = 0; k < K; ++k) {
-    for (int i = 0; i < 9; ++i) dgeo[(size_t)(kGeoStride * k + i)] = geo[10 * k + i];
-    dgeo[(size_t)(kGeoStride * k + 9)] = c[k];
+    double* o = dgeo.data() + (size_t)(kGeoStride * k);
+    for (int i = 0; i < 9; ++i) o[i] = geo[10 * k + i];
+    o[9] = c[k] * c[k];
     for (int f = 0; f < 4; ++f) {
       const int64_t slot = 4 * k + f;
       fo[(size_t)slot] = EToE[slot] >= 0 ? (uint8_t)((EToF[slot] & 3) | (EToO[slot] << 2)) : 0;
-      dgeo[(size_t)(kGeoStride * k + 10 + f)] = EToE[slot] >= 0 ? c[EToE[slot]] : c[k];
+      // grad lambda_f (lambda_0 = 1 - lambda_1 - lambda_2 - lambda_3)
+      double gl[3];
+      for (int d = 0; d < 3; ++d)
+        gl[d] = f == 0 ? -(geo[10 * k + d] + geo[10 * k + 3 + d] + geo[10 * k + 6 + d]) : geo[10 * k + 3 * (f - 1) + d];
+      const double gn = 2.0 * std::sqrt(gl[0] * gl[0] + gl[1] * gl[1] + gl[2] * gl[2]);
+      const double cp = EToE[slot] >= 0 ? c[EToE[slot]] : c[k];
+      o[10 + f] = c[k] * c[k] * gn / (c[k] + cp);  // kappa tau_p |g| / 2
+      o[14 + f] = (c[k] + cp) / (4.0 * gn);         // tau_u / (2 |g|)
     }
   }
   const std::vector<uint16_t> tab = build_tables(N);
