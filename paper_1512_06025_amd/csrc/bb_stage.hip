@@ -139,6 +139,7 @@ void bb_stage_kernel(StageArgs<T> A) {
   using S = Shape<N, T>;
   constexpr int Np = S::Np, Nfp = S::Nfp, E = S::E, NPL = S::NPL, NFI = S::NFI;
   constexpr int FB = S::FB, NV = S::NV, WPB = S::WPB, GEO = S::GEO;
+  constexpr int PK = sizeof(T) == 4 ? 4 : 1;
   constexpr bool kVol = (MODE != kRhsSurface);
   constexpr bool kSurf = (MODE != kRhsVolume);
   constexpr TabLayout L = tab_layout(N);
@@ -157,7 +158,9 @@ void bb_stage_kernel(StageArgs<T> A) {
   __shared__ uint32_t t_lvp[Np];
   __shared__ T t_lvc[3][Np];
   // per-wave buffers
-  __shared__ __attribute__((aligned(16))) T sq[WPB][E][4][Np];
+  // the element's coefficients, field-major in double, (p,u,v,w) packed into
+  // one 16-byte vector per node in float
+  __shared__ __attribute__((aligned(16))) T sq[WPB][E][4 / PK][Np][PK];
   __shared__ __attribute__((aligned(16))) T sfl[WPB][E][NV][Nfp];
   __shared__ __attribute__((aligned(16))) T slev[WPB][E][NV][Np];
   __shared__ __attribute__((aligned(16))) T sgeo[WPB][E][GEO];
@@ -332,7 +335,7 @@ void bb_stage_kernel(StageArgs<T> A) {
         const int el = v / Np;
         const int n = v - el * Np;
 #pragma unroll
-        for (int f = 0; f < 4; ++f) sq[w][el][f][n] = qv[r][f];
+        for (int f = 0; f < 4; ++f) sq[w][el][f / PK][n][f % PK] = qv[r][f];
       }
     }
     wave_lds_sync();
@@ -360,27 +363,33 @@ void bb_stage_kernel(StageArgs<T> A) {
         auto P = [&](int ai, int bi) { return nb[3 * ai + (bi < ai ? bi : bi - 1)]; };
         const T* ge = sgeo[w][el];
         T div = 0, gp[3] = {0, 0, 0};
-        // one field at a time: 13 coefficients live instead of 52
+        // one pack of PK fields at a time: 13 x PK coefficients live
 #pragma unroll
-        for (int f = 0; f < 4; ++f) {
-          const T fc = qv[r][f];
-          T Di[4];
+        for (int pk = 0; pk < 4 / PK; ++pk) {
+          T Di[PK][4];
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
-            T d = av[i] * fc;
+#pragma unroll
+            for (int c = 0; c < PK; ++c) Di[c][i] = av[i] * qv[r][pk * PK + c];
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
               if (b == i) continue;
-              d += av[b] * sq[w][el][f][P(i, b)];
-            }
-            Di[i] = d;
-          }
-          if (f == 0) {
+              const T* x = sq[w][el][pk][P(i, b)];
 #pragma unroll
-            for (int d = 0; d < 3; ++d)
-              gp[d] = ge[d] * Di[0] + ge[3 + d] * Di[1] + ge[6 + d] * Di[2] + ge[9 + d] * Di[3];
-          } else {
-            div += ge[f - 1] * Di[0] + ge[3 + f - 1] * Di[1] + ge[6 + f - 1] * Di[2] + ge[9 + f - 1] * Di[3];
+              for (int c = 0; c < PK; ++c) Di[c][i] += av[b] * x[c];
+            }
+          }
+#pragma unroll
+          for (int c = 0; c < PK; ++c) {
+            const int f = pk * PK + c;
+            if (f == 0) {
+#pragma unroll
+              for (int d = 0; d < 3; ++d)
+                gp[d] = ge[d] * Di[c][0] + ge[3 + d] * Di[c][1] + ge[6 + d] * Di[c][2] + ge[9 + d] * Di[c][3];
+            } else {
+              div += ge[f - 1] * Di[c][0] + ge[3 + f - 1] * Di[c][1] + ge[6 + f - 1] * Di[c][2] +
+                     ge[9 + f - 1] * Di[c][3];
+            }
           }
           __builtin_amdgcn_sched_barrier(0);
         }
@@ -406,7 +415,8 @@ void bb_stage_kernel(StageArgs<T> A) {
           T sp = 0, su = 0;
           if (e0 + el < K) {
             const int n = t_fnode[f * Nfp + gg];
-            const T pm = sq[w][el][0][n], um = sq[w][el][1][n], vm = sq[w][el][2][n], wm = sq[w][el][3][n];
+            const T pm = sq[w][el][0][n][0], um = sq[w][el][1 / PK][n][1 % PK], vm = sq[w][el][2 / PK][n][2 % PK],
+                    wm = sq[w][el][3 / PK][n][3 % PK];
             const T* fr = sgeo[w][el] + 16 + 8 * f;
             const T gx = fr[0], gy = fr[1], gz = fr[2];
             T jp, jgu;
