@@ -117,6 +117,29 @@ int bbdg_create(bbdg_solver** out, int N, int dtype, int64_t K,
                 const int32_t* EToE, const int8_t* EToF, const int8_t* EToO,
                 const double* geo, const double* c, int bc, int device);
 
+/* Dense nodal comparator (not the Bernstein-Bezier method): the same DG
+ * scheme (Section 2 flux, strong form of Section 3) in the Lagrange basis of
+ * the equispaced lattice (the BB control-point positions), with dense
+ * operators applied by MFMA (Section 4.2 describes the paper's nodal
+ * comparators).  Same arguments and validation as bbdg_create; the fields of
+ * such a solver are nodal values at the lattice points, in the coefficient
+ * order of bbdg_alpha_table.  bbdg_rhs, bbdg_run, bbdg_work_bytes and
+ * bbdg_destroy accept both kinds of handle. */
+int bbdg_nodal_create(bbdg_solver** out, int N, int dtype, int64_t K,
+                      const int32_t* EToE, const int8_t* EToF, const int8_t* EToO,
+                      const double* geo, const double* c, int bc, int device);
+
+/* The comparator's dense operators of order N, as built at create time (host,
+ * caller-allocated): dr (3 x Np x Np) with Dr_i = V (D^i - D^0) V^{-1}, so that
+ * grad f = sum_i grad(lambda_i) Dr_i f, and lift (Np x 4 Nfp), the face lifts
+ * V L^f Vf^{-1} of the four faces side by side (face f, face-local node g in
+ * column f Nfp + g).  V, Vf: Bernstein-Vandermonde matrices of the volume and
+ * face lattices. */
+int bbdg_nodal_operators(int N, double* dr, double* lift);
+
+/* 0 for a Bernstein-Bezier solver, 1 for a nodal comparator, BBDG_E_ARG for NULL. */
+int bbdg_basis(const bbdg_solver* s);
+
 /* Order, element type and element count of a solver. */
 int bbdg_info(const bbdg_solver* s, int* N, int* dtype, int64_t* K, int* Np);
 

@@ -7,10 +7,10 @@ streams only.
 """
 from ._lib import (BBDG_BC_PRESSURE_RELEASE, BBDG_BC_RIGID, BBDG_F32, BBDG_F64,
                    BBDG_RHS_FULL, BBDG_RHS_SURFACE, BBDG_RHS_VOLUME, BBDGError, load)
-from .solver import MeshData, Solver, alpha_table, mesh_geometry, np_count
+from .solver import MeshData, Solver, alpha_table, mesh_geometry, nodal_operators, np_count
 
 __all__ = [
-    "Solver", "MeshData", "alpha_table", "mesh_geometry", "np_count", "load", "BBDGError",
+    "Solver", "MeshData", "alpha_table", "mesh_geometry", "nodal_operators", "np_count", "load", "BBDGError",
     "BBDG_F64", "BBDG_F32", "BBDG_BC_RIGID", "BBDG_BC_PRESSURE_RELEASE",
     "BBDG_RHS_FULL", "BBDG_RHS_VOLUME", "BBDG_RHS_SURFACE",
 ]

@@ -30,6 +30,11 @@ SIGNATURES = {
     "bbdg_create": (_c.c_int, [_c.POINTER(_c.c_void_p), _c.c_int, _c.c_int, _c.c_int64,
                                _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p,
                                _c.c_int, _c.c_int]),
+    "bbdg_nodal_create": (_c.c_int, [_c.POINTER(_c.c_void_p), _c.c_int, _c.c_int, _c.c_int64,
+                                     _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p,
+                                     _c.c_int, _c.c_int]),
+    "bbdg_nodal_operators": (_c.c_int, [_c.c_int, _c.c_void_p, _c.c_void_p]),
+    "bbdg_basis": (_c.c_int, [_c.c_void_p]),
     "bbdg_info": (_c.c_int, [_c.c_void_p, _c.POINTER(_c.c_int), _c.POINTER(_c.c_int),
                              _c.POINTER(_c.c_int64), _c.POINTER(_c.c_int)]),
     "bbdg_rhs": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_int, _c.c_void_p]),

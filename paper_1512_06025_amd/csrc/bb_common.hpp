@@ -63,6 +63,19 @@ constexpr TabLayout tab_layout(int N) {
 // Orientation codes: index of the permutation (pi(0), pi(1), pi(2)).
 constexpr int kPerm[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
 
+// Padded sizes of the dense nodal operators: rows to MFMA tiles of 16,
+// contraction lengths to multiples of 4.
+struct NodalDims {
+  int NpP, Kv, Kl;
+};
+constexpr NodalDims nodal_dims(int N) {
+  NodalDims d{};
+  d.NpP = (np_of(N) + 15) / 16 * 16;
+  d.Kv = (np_of(N) + 3) / 4 * 4;
+  d.Kl = (4 * nfp_of(N) + 3) / 4 * 4;
+  return d;
+}
+
 enum StageMode { kStage = 0, kRhsFull = 1, kRhsVolume = 2, kRhsSurface = 3 };
 
 }  // namespace bbdg

@@ -26,6 +26,30 @@ struct StageArgs {
 template <typename T>
 hipError_t launch_stage(int N, int mode, const StageArgs<T>& a, hipStream_t stream);
 
+// Arguments of the dense nodal comparator stage kernel: the same fields,
+// geometry and connectivity plus the dense operators
+//   dr   [3][NpP][Kv]  Dr_i = V (D^i - D^0) V^{-1}, zero padded
+//   lift [NpP][Kl]     the four face lifts side by side, zero padded
+template <typename T>
+struct NodalArgs {
+  const T* qin;
+  T* qout;
+  T* res;
+  const double* geo;
+  const int32_t* etoe;
+  const uint8_t* etofo;
+  const uint16_t* tab;
+  const T* dr;
+  const T* lift;
+  int64_t K;
+  T rk_a, rk_b, dt;
+  int read_res;
+  int bc;
+};
+
+template <typename T>
+hipError_t launch_nodal_stage(int N, int mode, const NodalArgs<T>& a, hipStream_t stream);
+
 hipError_t launch_copy_probe(const void* src, void* dst, size_t bytes, hipStream_t stream);
 
 }  // namespace bbdg

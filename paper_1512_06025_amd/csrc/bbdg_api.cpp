@@ -18,7 +18,10 @@ using namespace bbdg;
 
 struct bbdg_solver {
   int N = 0, dtype = 0, bc = 0, device = 0;
+  int basis = 0;  // 0 Bernstein-Bezier, 1 dense nodal comparator
   int64_t K = 0;
+  void* d_dr = nullptr;    // nodal: [3][NpP][Kv] of the element type
+  void* d_lift = nullptr;  // nodal: [NpP][Kl]
   double* d_geo = nullptr;     // K x kGeoStride (see bb_common.hpp)
   int32_t* d_etoe = nullptr;   // K x 4
   uint8_t* d_etofo = nullptr;  // K x 4
@@ -131,31 +134,219 @@ StageArgs<T> base_args(const bbdg_solver* s) {
 }
 
 template <typename T>
+NodalArgs<T> nodal_args(const bbdg_solver* s);
+
+template <typename T>
+hipError_t launch_any(const bbdg_solver* s, int mode, const T* qin, T* qout, T* res, T rk_a, T rk_b, T dt,
+                      int read_res, hipStream_t st) {
+  if (s->basis == 0) {
+    StageArgs<T> a = base_args<T>(s);
+    a.qin = qin;
+    a.qout = qout;
+    a.res = res;
+    a.rk_a = rk_a;
+    a.rk_b = rk_b;
+    a.dt = dt;
+    a.read_res = read_res;
+    return launch_stage<T>(s->N, mode, a, st);
+  }
+  NodalArgs<T> a = nodal_args<T>(s);
+  a.qin = qin;
+  a.qout = qout;
+  a.res = res;
+  a.rk_a = rk_a;
+  a.rk_b = rk_b;
+  a.dt = dt;
+  a.read_res = read_res;
+  return launch_nodal_stage<T>(s->N, mode, a, st);
+}
+
+template <typename T>
 int run_typed(bbdg_solver* s, T* q, T* work, double dt, int64_t steps, hipStream_t st) {
   const int64_t n = 4 * s->K * (int64_t)np_of(s->N);
   T* res = work;
-  T* other = work + n;
   T* cur = q;
-  T* nxt = other;
-  StageArgs<T> a = base_args<T>(s);
-  a.res = res;
-  a.dt = (T)dt;
+  T* nxt = work + n;
   for (int64_t it = 0; it < steps; ++it) {
     for (int st5 = 0; st5 < 5; ++st5) {
-      a.qin = cur;
-      a.qout = nxt;
-      a.rk_a = (T)kRkA[st5];
-      a.rk_b = (T)kRkB[st5];
-      a.read_res = (st5 != 0);
-      if (launch_stage<T>(s->N, kStage, a, st) != hipSuccess) return BBDG_E_LAUNCH;
+      if (launch_any<T>(s, kStage, cur, nxt, res, (T)kRkA[st5], (T)kRkB[st5], (T)dt, st5 != 0, st) != hipSuccess)
+        return BBDG_E_LAUNCH;
       std::swap(cur, nxt);
     }
   }
   if (cur != q) {
-    if (hipMemcpyAsync(q, cur, n * sizeof(T), hipMemcpyDeviceToDevice, st) != hipSuccess)
-      return BBDG_E_DEVICE;
+    if (hipMemcpyAsync(q, cur, n * sizeof(T), hipMemcpyDeviceToDevice, st) != hipSuccess) return BBDG_E_DEVICE;
   }
   return BBDG_OK;
+}
+
+// ---- dense nodal comparator operators --------------------------------------
+
+double binom(int n, int k) {
+  if (k < 0 || k > n) return 0.0;
+  double r = 1.0;
+  for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
+  return r;
+}
+
+double fact(int n) {
+  double r = 1.0;
+  for (int i = 2; i <= n; ++i) r *= i;
+  return r;
+}
+
+// In-place inverse of a dense n x n row-major matrix (Gauss-Jordan, partial pivoting).
+bool invert(std::vector<double>& a, int n) {
+  std::vector<double> inv((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) inv[(size_t)i * n + i] = 1.0;
+  for (int c = 0; c < n; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < n; ++r)
+      if (std::fabs(a[(size_t)r * n + c]) > std::fabs(a[(size_t)piv * n + c])) piv = r;
+    if (a[(size_t)piv * n + c] == 0.0) return false;
+    if (piv != c)
+      for (int j = 0; j < n; ++j) {
+        std::swap(a[(size_t)c * n + j], a[(size_t)piv * n + j]);
+        std::swap(inv[(size_t)c * n + j], inv[(size_t)piv * n + j]);
+      }
+    const double d = 1.0 / a[(size_t)c * n + c];
+    for (int j = 0; j < n; ++j) {
+      a[(size_t)c * n + j] *= d;
+      inv[(size_t)c * n + j] *= d;
+    }
+    for (int r = 0; r < n; ++r) {
+      if (r == c) continue;
+      const double f = a[(size_t)r * n + c];
+      if (f == 0.0) continue;
+      for (int j = 0; j < n; ++j) {
+        a[(size_t)r * n + j] -= f * a[(size_t)c * n + j];
+        inv[(size_t)r * n + j] -= f * inv[(size_t)c * n + j];
+      }
+    }
+  }
+  a.swap(inv);
+  return true;
+}
+
+std::vector<double> matmul(const std::vector<double>& a, const std::vector<double>& b, int n, int k, int m) {
+  std::vector<double> c((size_t)n * m, 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int l = 0; l < k; ++l) {
+      const double x = a[(size_t)i * k + l];
+      if (x == 0.0) continue;
+      for (int j = 0; j < m; ++j) c[(size_t)i * m + j] += x * b[(size_t)l * m + j];
+    }
+  return c;
+}
+
+// Bernstein-Vandermonde matrix of degree N on the equispaced lattice of a
+// simplex with `dim`+1 barycentric coordinates: V[p][b] = B_b(lattice point p).
+std::vector<double> vandermonde(const std::vector<std::vector<int>>& idx, int N) {
+  const int n = (int)idx.size();
+  std::vector<double> V((size_t)n * n);
+  for (int p = 0; p < n; ++p)
+    for (int b = 0; b < n; ++b) {
+      double v = fact(N);
+      for (size_t i = 0; i < idx[b].size(); ++i) {
+        v /= fact(idx[b][i]);
+        v *= std::pow((double)idx[p][i] / N, idx[b][i]);
+      }
+      V[(size_t)p * n + b] = v;
+    }
+  return V;
+}
+
+// Dense nodal operators of order N: Dr_i = V (D^i - D^0) V^{-1} (i = 1..3) and
+// the lift [V L^f Vf^{-1}]_f with L^f = E_L^f L_0 from the closed forms of
+// the factorisation (Section 3.1.2).  Returned padded to NodalDims.
+bool nodal_operators(int N, std::vector<double>& dr, std::vector<double>& lift) {
+  const NodalDims nd = nodal_dims(N);
+  const int Np = np_of(N), Nfp = nfp_of(N);
+  const auto A = alphas(N);
+  std::vector<std::vector<int>> vidx(Np), fidx;
+  for (int n = 0; n < Np; ++n) vidx[n] = {A[n][0], A[n][1], A[n][2], A[n][3]};
+  for (int g2 = 0; g2 <= N; ++g2)
+    for (int g1 = 0; g1 <= N - g2; ++g1) fidx.push_back({N - g1 - g2, g1, g2});
+  std::vector<double> V = vandermonde(vidx, N), Vi = V;
+  std::vector<double> Vf = vandermonde(fidx, N);
+  if (!invert(Vi, Np) || !invert(Vf, Nfp)) return false;
+  // barycentric derivatives in the BB basis (row form of Lemma 1)
+  std::vector<double> Db[4];
+  for (int i = 0; i < 4; ++i) {
+    Db[i].assign((size_t)Np * Np, 0.0);
+    for (int n = 0; n < Np; ++n)
+      for (int j = 0; j < 4; ++j) {
+        if (A[n][j] == 0) continue;
+        std::array<int, 4> c = A[n];
+        c[i] += 1;
+        c[j] -= 1;
+        Db[i][(size_t)n * Np + vol_index(N, c[1], c[2], c[3])] += A[n][j];
+      }
+  }
+  dr.assign((size_t)3 * nd.NpP * nd.Kv, 0.0);
+  for (int i = 1; i <= 3; ++i) {
+    std::vector<double> d((size_t)Np * Np);
+    for (size_t t = 0; t < d.size(); ++t) d[t] = Db[i][t] - Db[0][t];
+    const std::vector<double> m = matmul(matmul(V, d, Np, Np, Np), Vi, Np, Np, Np);
+    for (int r = 0; r < Np; ++r)
+      for (int c = 0; c < Np; ++c) dr[((size_t)(i - 1) * nd.NpP + r) * nd.Kv + c] = m[(size_t)r * Np + c];
+  }
+  // L_0 on face-local indices
+  std::vector<double> L0((size_t)Nfp * Nfp, 0.0);
+  for (int a = 0; a < Nfp; ++a) {
+    const auto& b = fidx[a];
+    L0[(size_t)a * Nfp + a] = 0.5 * ((b[0] + 1) * (b[0] + 1) + (b[1] + 1) * (b[1] + 1) + (b[2] + 1) * (b[2] + 1));
+    for (int k = 0; k < 3; ++k)
+      for (int m = 0; m < 3; ++m) {
+        if (k == m || b[m] == 0) continue;
+        int c[3] = {b[0], b[1], b[2]};
+        c[k] += 1;
+        c[m] -= 1;
+        L0[(size_t)a * Nfp + tri_row(c[2], N) + c[1]] += 0.5 * (b[k] + 1) * b[m];
+      }
+  }
+  lift.assign((size_t)nd.NpP * nd.Kl, 0.0);
+  for (int f = 0; f < 4; ++f) {
+    int fv[3];
+    face_verts(f, fv);
+    // E_L^f (Np x Nfp): (-1)^{a_f}/(1+a_f) prod_m C(g_m, a_{v_m})
+    std::vector<double> EL((size_t)Np * Nfp, 0.0);
+    for (int n = 0; n < Np; ++n) {
+      const int af = A[n][f];
+      const double s = ((af & 1) ? -1.0 : 1.0) / (1.0 + af);
+      for (int g = 0; g < Nfp; ++g) {
+        double v = s;
+        for (int m = 0; m < 3; ++m) v *= binom(fidx[g][m], A[n][fv[m]]);
+        EL[(size_t)n * Nfp + g] = v;
+      }
+    }
+    const std::vector<double> Lb = matmul(EL, L0, Np, Nfp, Nfp);
+    const std::vector<double> Ln = matmul(matmul(V, Lb, Np, Np, Nfp), Vf, Np, Nfp, Nfp);
+    for (int r = 0; r < Np; ++r)
+      for (int g = 0; g < Nfp; ++g) lift[(size_t)r * nd.Kl + f * Nfp + g] = Ln[(size_t)r * Nfp + g];
+  }
+  return true;
+}
+
+template <typename T>
+bool upload_as(const std::vector<double>& h, void** d) {
+  std::vector<T> t(h.begin(), h.end());
+  if (hipMalloc(d, t.size() * sizeof(T)) != hipSuccess) return false;
+  return hipMemcpy(*d, t.data(), t.size() * sizeof(T), hipMemcpyHostToDevice) == hipSuccess;
+}
+
+template <typename T>
+NodalArgs<T> nodal_args(const bbdg_solver* s) {
+  NodalArgs<T> a{};
+  a.geo = s->d_geo;
+  a.etoe = s->d_etoe;
+  a.etofo = s->d_etofo;
+  a.tab = s->d_tab;
+  a.dr = (const T*)s->d_dr;
+  a.lift = (const T*)s->d_lift;
+  a.K = s->K;
+  a.bc = s->bc;
+  return a;
 }
 
 void free_solver(bbdg_solver* s) {
@@ -164,6 +355,8 @@ void free_solver(bbdg_solver* s) {
   if (s->d_etoe) (void)hipFree(s->d_etoe);
   if (s->d_etofo) (void)hipFree(s->d_etofo);
   if (s->d_tab) (void)hipFree(s->d_tab);
+  if (s->d_dr) (void)hipFree(s->d_dr);
+  if (s->d_lift) (void)hipFree(s->d_lift);
   delete s;
 }
 
@@ -300,8 +493,8 @@ int bbdg_mesh_geometry(int64_t K, int64_t Nv, const double* VX, const int32_t* E
   return BBDG_OK;
 }
 
-int bbdg_create(bbdg_solver** out, int N, int dtype, int64_t K, const int32_t* EToE, const int8_t* EToF,
-                const int8_t* EToO, const double* geo, const double* c, int bc, int device) {
+static int create_impl(bbdg_solver** out, int N, int dtype, int64_t K, const int32_t* EToE, const int8_t* EToF,
+                       const int8_t* EToO, const double* geo, const double* c, int bc, int device, int basis) {
   if (!out) return BBDG_E_ARG;
   *out = nullptr;
   if (N < 1 || N > kMaxOrder) return BBDG_E_ORDER;
@@ -334,6 +527,7 @@ int bbdg_create(bbdg_solver** out, int N, int dtype, int64_t K, const int32_t* E
   s->bc = bc;
   s->device = device;
   s->K = K;
+  s->basis = basis;
 
   std::vector<double> dgeo((size_t)(kGeoStride * K));
   std::vector<uint8_t> fo((size_t)(4 * K));
@@ -363,12 +557,51 @@ int bbdg_create(bbdg_solver** out, int N, int dtype, int64_t K, const int32_t* E
   ok = ok && hipMemcpy(s->d_etoe, EToE, (size_t)(4 * K) * sizeof(int32_t), hipMemcpyHostToDevice) == hipSuccess;
   ok = ok && hipMemcpy(s->d_etofo, fo.data(), fo.size(), hipMemcpyHostToDevice) == hipSuccess;
   ok = ok && hipMemcpy(s->d_tab, tab.data(), tab.size() * sizeof(uint16_t), hipMemcpyHostToDevice) == hipSuccess;
+  if (ok && basis == 1) {
+    std::vector<double> dr, lift;
+    if (!nodal_operators(N, dr, lift)) {
+      free_solver(s);
+      return BBDG_E_ARG;
+    }
+    ok = dtype == BBDG_F64 ? (upload_as<double>(dr, &s->d_dr) && upload_as<double>(lift, &s->d_lift))
+                           : (upload_as<float>(dr, &s->d_dr) && upload_as<float>(lift, &s->d_lift));
+  }
   if (!ok) {
     free_solver(s);
     return BBDG_E_DEVICE;
   }
   *out = s;
   return BBDG_OK;
+}
+
+int bbdg_create(bbdg_solver** out, int N, int dtype, int64_t K, const int32_t* EToE, const int8_t* EToF,
+                const int8_t* EToO, const double* geo, const double* c, int bc, int device) {
+  return create_impl(out, N, dtype, K, EToE, EToF, EToO, geo, c, bc, device, 0);
+}
+
+int bbdg_nodal_create(bbdg_solver** out, int N, int dtype, int64_t K, const int32_t* EToE, const int8_t* EToF,
+                      const int8_t* EToO, const double* geo, const double* c, int bc, int device) {
+  return create_impl(out, N, dtype, K, EToE, EToF, EToO, geo, c, bc, device, 1);
+}
+
+int bbdg_nodal_operators(int N, double* dr, double* lift) {
+  if (N < 1 || N > kMaxOrder) return BBDG_E_ORDER;
+  if (!dr || !lift) return BBDG_E_ARG;
+  std::vector<double> d, l;
+  if (!nodal_operators(N, d, l)) return BBDG_E_ARG;
+  const NodalDims nd = nodal_dims(N);
+  const int Np = np_of(N), Nfp = nfp_of(N);
+  for (int i = 0; i < 3; ++i)
+    for (int r = 0; r < Np; ++r)
+      for (int c = 0; c < Np; ++c) dr[((size_t)i * Np + r) * Np + c] = d[((size_t)i * nd.NpP + r) * nd.Kv + c];
+  for (int r = 0; r < Np; ++r)
+    for (int c = 0; c < 4 * Nfp; ++c) lift[(size_t)r * 4 * Nfp + c] = l[(size_t)r * nd.Kl + c];
+  return BBDG_OK;
+}
+
+int bbdg_basis(const bbdg_solver* s) {
+  if (!s) return BBDG_E_ARG;
+  return s->basis;
 }
 
 int bbdg_info(const bbdg_solver* s, int* N, int* dtype, int64_t* K, int* Np) {
@@ -396,17 +629,10 @@ int bbdg_rhs(bbdg_solver* s, const void* q, void* rhs, int mode, void* stream) {
   if (hipSetDevice(s->device) != hipSuccess) return BBDG_E_DEVICE;
   hipStream_t st = (hipStream_t)stream;
   hipError_t e;
-  if (s->dtype == BBDG_F64) {
-    StageArgs<double> x = base_args<double>(s);
-    x.qin = (const double*)q;
-    x.qout = (double*)rhs;
-    e = launch_stage<double>(s->N, km, x, st);
-  } else {
-    StageArgs<float> x = base_args<float>(s);
-    x.qin = (const float*)q;
-    x.qout = (float*)rhs;
-    e = launch_stage<float>(s->N, km, x, st);
-  }
+  if (s->dtype == BBDG_F64)
+    e = launch_any<double>(s, km, (const double*)q, (double*)rhs, nullptr, 0.0, 0.0, 0.0, 0, st);
+  else
+    e = launch_any<float>(s, km, (const float*)q, (float*)rhs, nullptr, 0.f, 0.f, 0.f, 0, st);
   return e == hipSuccess ? BBDG_OK : BBDG_E_LAUNCH;
 }
 

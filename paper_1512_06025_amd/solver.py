@@ -48,13 +48,25 @@ def _stream_ptr(stream):
     return ctypes.c_void_p(s.cuda_stream)
 
 
+def nodal_operators(N):
+    """(dr (3, Np, Np), lift (Np, 4 Nfp)) of the dense nodal comparator."""
+    Np = np_count(N)
+    Nfp = (N + 1) * (N + 2) // 2
+    dr = np.zeros((3, Np, Np))
+    lift = np.zeros((Np, 4 * Nfp))
+    check(load().bbdg_nodal_operators(int(N), dr.ctypes.data, lift.ctypes.data), "bbdg_nodal_operators")
+    return dr, lift
+
+
 class Solver:
     """One solver handle: order N, element type, mesh, wavespeed, boundary condition.
 
+    basis="bb" is the Bernstein-Bezier solver; basis="nodal" the dense nodal
+    comparator (fields are then nodal values at the lattice points).
     Field tensors are torch CUDA tensors of shape (4, K, Np) with dtype
     float64 (dtype="f64") or float32 (dtype="f32")."""
 
-    def __init__(self, N, mesh, c, dtype="f64", bc="rigid", device=0):
+    def __init__(self, N, mesh, c, dtype="f64", bc="rigid", device=0, basis="bb"):
         import torch
         self.N = int(N)
         self.dtype = dtype
@@ -66,10 +78,12 @@ class Solver:
         self.device = torch.device("cuda", device)
         c = np.ascontiguousarray(np.broadcast_to(np.asarray(c, dtype=np.float64), (self.K,)))
         h = ctypes.c_void_p()
-        check(load().bbdg_create(ctypes.byref(h), self.N, self.code, self.K,
-                                 mesh.EToE.ctypes.data, mesh.EToF.ctypes.data, mesh.EToO.ctypes.data,
-                                 mesh.geo.ctypes.data, c.ctypes.data, bcode, int(device)),
-              "bbdg_create")
+        create = {"bb": load().bbdg_create, "nodal": load().bbdg_nodal_create}[basis]
+        self.basis = basis
+        check(create(ctypes.byref(h), self.N, self.code, self.K,
+                     mesh.EToE.ctypes.data, mesh.EToF.ctypes.data, mesh.EToO.ctypes.data,
+                     mesh.geo.ctypes.data, c.ctypes.data, bcode, int(device)),
+              "bbdg_create" if basis == "bb" else "bbdg_nodal_create")
         self._h = h
         self._work = None
 

@@ -107,3 +107,58 @@ def test_run_is_bitwise_repeatable():
     s.run(b, 1e-3, 3)
     assert torch.equal(a, b)
     s.close()
+
+
+# ---- dense nodal comparator -------------------------------------------------
+# Nodal values are V c (V the Bernstein-Vandermonde matrix of the lattice);
+# the comparator's result is compared with V (oracle RHS of c).  The change of
+# basis (condition number of V up to ~1e3 at N = 9) loosens the FP64 bar to
+# 1e-10; FP32 operators and dense sums of up to 4 Nfp terms give 1e-4.
+NODAL_TOL = {"f64": 1e-10, "f32": 1e-4}
+
+
+def _lattice_vandermonde(N):
+    from oracle import bernstein as bb
+    return dg.bernstein_eval(N, np.array(bb.multi_indices(N), float) / N)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("N", list(range(1, 10)))
+def test_nodal_rhs_parity(N, dtype):
+    P, mesh, c, prob = _setup(2, N, drop_last=5)
+    V = _lattice_vandermonde(N)
+    cq = workload.random_coeffs(prob.K, prob.Np)
+    x = cq @ V.T
+    if dtype == "f32":
+        x = x.astype(np.float32).astype(np.float64)
+        cq = x @ np.linalg.inv(V).T
+    s = P.Solver(N, mesh, c, dtype=dtype, basis="nodal")
+    xd = _to_dev(x, dtype)
+    for mode, kw in ((P.BBDG_RHS_VOLUME, dict(surface=False)),
+                     (P.BBDG_RHS_SURFACE, dict(volume=False)),
+                     (P.BBDG_RHS_FULL, {})):
+        got = _host(s.rhs(xd, mode))
+        want = prob.rhs(cq, **kw) @ V.T
+        err = _rel(got, want)
+        assert err < NODAL_TOL[dtype], (N, dtype, mode, err)
+    s.close()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_nodal_run_parity_c1(dtype):
+    import paper_1512_06025_amd as P
+    cfg, VX, EToV, c = workload.build_preset("c1")
+    prob = dg.Problem(VX, EToV, cfg["N"], c)
+    V = _lattice_vandermonde(cfg["N"])
+    q0 = dg.initial_state(prob, workload.standing_mode_p0)
+    x0 = q0 @ V.T
+    if dtype == "f32":
+        x0 = x0.astype(np.float32).astype(np.float64)
+        q0 = x0 @ np.linalg.inv(V).T
+    want = prob.lsrk4(q0, cfg["dt"], cfg["steps"]) @ V.T
+    s = P.Solver(cfg["N"], P.mesh_geometry(VX, EToV), c, dtype=dtype, basis="nodal")
+    xd = _to_dev(x0, dtype)
+    s.run(xd, cfg["dt"], cfg["steps"])
+    err = _rel(_host(xd), want)
+    assert err < NODAL_TOL[dtype], err
+    s.close()
