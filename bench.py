@@ -58,8 +58,8 @@ def algorithmic_bytes_per_element(N, word):
     return word * (16 * Np + 16 * Nfp + 14) + 20
 
 
-def time_gpu(P, torch, N, mesh, c, q0, dt, steps, warmup, dtype):
-    s = P.Solver(N, mesh, c, dtype=dtype)
+def time_gpu(P, torch, N, mesh, c, q0, dt, steps, warmup, dtype, basis="bb"):
+    s = P.Solver(N, mesh, c, dtype=dtype, basis=basis)
     q = torch.from_numpy(q0).to("cuda", s.torch_dtype)
     stream = torch.cuda.current_stream()
     if warmup:
@@ -75,6 +75,40 @@ def time_gpu(P, torch, N, mesh, c, q0, dt, steps, warmup, dtype):
     finite = bool(torch.isfinite(q).all().item())
     s.close()
     return ms, finite
+
+
+def time_batched(P, torch, workload, steps):
+    """64 shots with Ricker point sources on 24,576 tets, N = 4, FP32: all
+    5 * steps stages in one persistent launch (waves per workgroup autotuned)."""
+    cfg, VX, EToV, c = workload.build_preset("c4")
+    N, K, Np, S, dt = cfg["N"], cfg["K"], cfg["Np"], cfg["shots"], cfg["dt"]
+    mesh = P.mesh_geometry(VX, EToV)
+    bs = P.BatchedSolver(N, mesh, c, S, sources=workload.source_positions(S), receivers=workload.receiver_grid(),
+                         f0=cfg["f0"], ts=cfg["ts"], dtype="f32")
+    wpb = bs.tune()
+    stream = torch.cuda.current_stream()
+    q = bs.empty_state()
+    bs.run(q, dt, 2, stream=stream)  # warm-up launch
+    q.zero_()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    tr = bs.run(q, dt, steps, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    stages = 5 * steps
+    stage_us = ms * 1e3 / stages
+    gbs = algorithmic_bytes_per_element(N, 4) * K * S / (stage_us * 1e-6) / 1e9
+    finite = bool(torch.isfinite(q).all().item() and torch.isfinite(tr).all().item())
+    bs.close()
+    return {"workload": "%d shots, Ricker f0=%g, %d receivers, unit cube %d^3x6 = %d tets, N=%d, c~U[%g,%g], "
+                        "FP32, %d steps in one persistent launch" % (S, cfg["f0"], 64, cfg["n"], K, N,
+                                                                     cfg["c"][0], cfg["c"][1], steps),
+            "value": 4.0 * K * Np * S * stages / (ms * 1e-3), "unit": "DoF-stage/s", "ms_total": ms,
+            "stage_us": stage_us, "achieved_GBs": gbs, "frac": gbs / HBM_PEAK_GBS, "waves_per_workgroup": wpb,
+            "finite": finite}
 
 
 def copy_probe(torch, P, nbytes=1 << 30, reps=20):
@@ -129,6 +163,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=1)
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-nodal", action="store_true", help="skip the dense nodal comparator")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 64-shot batched workload")
+    ap.add_argument("--batched-steps", type=int, default=500)
     ap.add_argument("--no-copy-probe", action="store_true")
     ap.add_argument("--copy-probe-only", action="store_true",
                     help="only run the streaming-copy probe (counter calibration)")
@@ -194,8 +231,8 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": recorded_traffic("bb_stage_kernel<%d, double, 0>" % N, args.config),
-            "kernel": "bb_stage_kernel<%d, double, 0>" % N,
+            "traffic": recorded_traffic("bb_stage_kernel<%d, double, 0, 4>" % N, args.config),
+            "kernel": "bb_stage_kernel<%d, double, 0, 4>" % N,
             "bytes_per_launch": bytes_launch,
             "avg_launch_us": stage_us,
         },
@@ -206,6 +243,20 @@ def main():
         a32 = algorithmic_bytes_per_element(N, 4) * K / (st32 * 1e-6) / 1e9
         out["fp32"] = {"value": dof * stages / (ms32 * 1e-3), "ms_per_step": ms32 / args.steps,
                        "stage_us": st32, "achieved_GBs": a32, "frac": a32 / HBM_PEAK_GBS, "finite": ok32}
+    if not args.no_nodal:
+        x0 = ic.initial_state(N, VX, EToV, workload.INITIAL_FIELDS[cfg["ic"]], basis="nodal")
+        nod = {}
+        for dt_name, bb_ms in (("f64", ms64), ("f32", out.get("fp32", {}).get("ms_per_step", 0) * args.steps)):
+            if dt_name == "f32" and args.no_fp32:
+                continue
+            msn, okn = time_gpu(P, torch, N, mesh, c, x0, dt, args.steps, args.warmup, dt_name, basis="nodal")
+            flop = K * (24 * Np * Np + 32 * Np * Nfp)  # dense volume + lift per stage
+            nod[dt_name] = {"value": dof * stages / (msn * 1e-3), "stage_us": msn * 1e3 / stages,
+                            "tflops": flop * stages / (msn * 1e-3) / 1e12, "finite": okn,
+                            "bb_speedup": msn / bb_ms}
+        out["nodal"] = nod
+    if not args.no_batched:
+        out["batched"] = time_batched(P, torch, workload, args.batched_steps)
     if not args.no_copy_probe:
         cp = copy_probe(torch, P)
         out["roofline"]["copy_probe_GBs"] = cp["GBs"]

@@ -73,6 +73,8 @@ extern "C" {
 #define BBDG_E_DEVICE (-7)    /* HIP runtime error: device selection, allocation, copy */
 #define BBDG_E_LAUNCH (-8)    /* kernel launch failed */
 #define BBDG_E_MODE (-9)      /* unknown right-hand-side mode */
+#define BBDG_E_OUTSIDE (-10)  /* a point lies in no element of the mesh */
+#define BBDG_E_RESIDENT (-11) /* a persistent grid that cannot be co-resident on the device */
 
 enum { BBDG_F64 = 0, BBDG_F32 = 1 };
 
@@ -157,6 +159,81 @@ size_t bbdg_work_bytes(const bbdg_solver* s);
  * contents on entry are ignored.  steps >= 0, dt finite. */
 int bbdg_run(bbdg_solver* s, void* q, void* work, double t0, double dt, int64_t steps,
              void* stream);
+
+/* ---- Batched shots: point sources and receivers ---------------------------
+ * The paper's experiments have no forcing (f = 0 in Section 2); the batched
+ * path adds the standard seismic source term to the pressure equation,
+ *   (1/kappa) p_t + div u = w(t) delta(x - x_s),
+ * discretised by the same Galerkin projection that defines the DG scheme
+ * (the delta tested against every basis function of the element holding
+ * x_s), and records receivers p(x_r, t) = sum_alpha p_alpha B_alpha(lambda(x_r))
+ * (the Bernstein expansion of Section 3.1).  The wavelet is the Ricker
+ * w(t) = (1 - 2 pi^2 f0^2 (t - ts)^2) exp(-pi^2 f0^2 (t - ts)^2). */
+
+/* Point location (host).  For each of n points xyz (n x 3 double), elem[i]
+ * is the lowest-numbered element whose barycentric coordinates of the point
+ * are all >= -1e-10, and bary (n x 4 double) holds those coordinates with
+ * negative values set to 0 and renormalised to sum 1.  VX, EToV as in
+ * bbdg_mesh_geometry.  Returns BBDG_E_OUTSIDE when a point lies in no element
+ * (its elem entry is -1; the other points are still filled). */
+int bbdg_locate_points(int64_t K, int64_t Nv, const double* VX, const int32_t* EToV,
+                       int64_t n, const double* xyz, int32_t* elem, double* bary);
+
+/* Bernstein polynomials of order N at n barycentric points (host): out
+ * (n x Np double) holds B_alpha(bary_i) = N!/alpha! prod_j lambda_j^alpha_j
+ * (Section 3.1) in coefficient order.  Receiver weights are these values. */
+int bbdg_bernstein_eval(int N, int64_t n, const double* bary, double* out);
+
+/* Point-source vectors (host).  coef (n x Np double): for a point with
+ * barycentric coordinates bary[i] in element elem[i],
+ *   kappa_k (M^k)^{-1} B(lambda),   M^k = V_k m,
+ *   m_ab = (N!)^2/(a! b!) 3! (a+b)!/(2N+3)!,
+ * the element mass matrix of the Bernstein basis (exact simplex integral;
+ * V_k = 4 J_k / 3 the element volume), so that adding w(t) coef to the
+ * pressure right-hand side of element k is the projected source term above.
+ * Fails with BBDG_E_ARG for an element id outside 0..K-1. */
+int bbdg_source_coeffs(const bbdg_solver* s, int64_t n, const int32_t* elem, const double* bary,
+                       double* coef);
+
+/* Bytes of device work space that bbdg_run_batched needs for `shots` shots:
+ * the LSRK residual and a second field buffer, 2 * shots * 4 * K * Np
+ * elements. */
+size_t bbdg_batched_work_bytes(const bbdg_solver* s, int64_t shots);
+
+/* Advances `shots` independent states on the solver's mesh and wavespeed by
+ * `steps` LSRK4 steps of size dt from time t0, in ONE persistent cooperative
+ * kernel launch (grid-wide barriers between the 5 * steps stages).
+ *   q:        device (shots, 4, K, Np), in/out (shot-major; each shot is a
+ *             (4, K, Np) field as above).
+ *   src_elem: device int32 (shots): source element of each shot, or -1 for a
+ *             shot without source; NULL = no sources at all.
+ *   src_coef: device (shots x Np) of the solver's element type: the
+ *             bbdg_source_coeffs vector of each shot's source.
+ *   f0, ts:   Ricker peak frequency (> 0) and delay; the wavelet is evaluated
+ *             at each stage time t + c_s dt.
+ *   R, rec_elem, rec_coef: R >= 0 receivers shared by all shots: device int32
+ *             element ids (R) and device (R x Np) weights B_alpha(lambda_r).  A
+ *             receiver whose element id is outside 0..K-1 records NaN.
+ *   traces:   device (steps, shots, R) of the element type: the pressure at
+ *             every receiver after every step.  May be NULL when R = 0.
+ *   work:     device, >= bbdg_batched_work_bytes(s, shots), 256-byte aligned.
+ *   wpb:      wavefronts per workgroup, 1, 2 or 4; 0 = the value
+ *             bbdg_tune_batched chose for this shot count (4 if not tuned).
+ * shots * ceil(K / E) must stay below 2^32 (E = elements per wavefront).
+ * Fails with BBDG_E_RESIDENT, before anything runs, if the grid cannot be
+ * co-resident. */
+int bbdg_run_batched(bbdg_solver* s, void* q, int64_t shots, const int32_t* src_elem,
+                     const void* src_coef, double f0, double ts, int R, const int32_t* rec_elem,
+                     const void* rec_coef, void* traces, void* work, double t0, double dt,
+                     int64_t steps, int wpb, void* stream);
+
+/* Autotuner of the batched launch shape: times two-step batched runs of
+ * `shots` zero states for every wavefronts-per-workgroup candidate (1, 2, 4),
+ * stores the fastest in the handle (used by bbdg_run_batched with wpb = 0)
+ * and returns it in *wpb.  scratch: device, >= bbdg_batched_work_bytes(s,
+ * shots) + shots * 4 * K * Np elements, 256-byte aligned; its contents are
+ * overwritten.  Synchronises `stream`. */
+int bbdg_tune_batched(bbdg_solver* s, int64_t shots, void* scratch, int* wpb, void* stream);
 
 /* Measurement aid, not part of the method: copies `bytes` (a multiple of 16,
  * both pointers 16-byte aligned, no overlap) from device buffer src to dst

@@ -142,17 +142,95 @@ class Problem:
         return out
 
     # -- time stepping ---------------------------------------------------------
-    def lsrk4(self, q, dt, steps, callback=None):
-        """Advance q by `steps` LSRK4 steps of size dt; returns the new q."""
+    def lsrk4(self, q, dt, steps, callback=None, forcing=None, t0=0.0):
+        """Advance q by `steps` LSRK4 steps of size dt from time t0; returns the
+        new q.  forcing(t), if given, is added to the right-hand side of the
+        stage at time t = t_n + c_s dt (LSRK_C)."""
         q = np.array(q, dtype=np.float64, copy=True)
         res = np.zeros_like(q)
         for n in range(steps):
             for s in range(5):
-                res = LSRK_A[s] * res + dt * self.rhs(q)
+                r = self.rhs(q)
+                if forcing is not None:
+                    r = r + forcing(t0 + n * dt + LSRK_C[s] * dt)
+                res = LSRK_A[s] * res + dt * r
                 q = q + LSRK_B[s] * res
             if callback is not None:
                 callback(n + 1, q)
         return q
+
+    # -- point sources and receivers -------------------------------------------
+    # The paper's experiments are unforced; a seismic point source enters the
+    # pressure equation as (1/kappa) p_t + div u = w(t) delta(x - x_s).  Its
+    # Galerkin projection on the element k holding x_s (the same test
+    # functions as the DG scheme, Section 2) is
+    #   dp_k/dt += w(t) kappa_k (M^k)^{-1} B(lambda(x_s)),   M^k = V_k m.
+    def locate(self, pts, tol=1e-10):
+        """Lowest-numbered element containing each point, with its barycentric
+        coordinates (negatives below tol set to 0, renormalised).  Returns
+        (elem (P,), lam (P, 4)); elem is -1 for a point outside the mesh."""
+        pts = np.atleast_2d(np.asarray(pts, dtype=np.float64))
+        g = self.geo
+        elem = np.full(pts.shape[0], -1, dtype=np.int64)
+        lam = np.zeros((pts.shape[0], 4))
+        for i, x in enumerate(pts):
+            # lambda_j(x) = 1/4 + grad(lambda_j) . (x - centroid) is affine
+            cen = g.X.mean(axis=1)
+            L = 0.25 + np.einsum("kjd,kd->kj", g.grad_lambda, x[None, :] - cen)
+            inside = np.nonzero(np.all(L >= -tol, axis=1))[0]
+            if inside.size:
+                k = inside[0]
+                l = np.clip(L[k], 0.0, None)
+                elem[i], lam[i] = k, l / l.sum()
+        return elem, lam
+
+    def point_source_vector(self, k, lam):
+        """kappa_k (V_k m)^{-1} B(lambda): (Np,) pressure right-hand side of a
+        unit point source in element k at barycentric coordinates lam."""
+        m = bb.mass_exact(self.N)
+        b = bernstein_eval(self.N, np.asarray(lam, dtype=np.float64)[None, :])[0]
+        x = bb._ld_gauss_solve(bb._frac_to_ld(m), np.asarray(b, dtype=np.longdouble)[:, None])[:, 0]
+        return (self.kappa[k] / self.geo.volume[k]) * np.asarray(x, dtype=np.float64)
+
+    def point_source(self, k, lam, f0, ts):
+        """forcing(t) for lsrk4: a Ricker point source in element k."""
+        vec = self.point_source_vector(k, lam)
+
+        def forcing(t):
+            out = np.zeros((4, self.K, self.Np))
+            out[0, k] = ricker(t, f0, ts) * vec
+            return out
+        return forcing
+
+    def receiver_weights(self, lam):
+        """B_alpha(lambda_r) for receivers at barycentric points lam (R, 4)."""
+        return bernstein_eval(self.N, np.atleast_2d(np.asarray(lam, dtype=np.float64)))
+
+    def run_shots(self, q0, dt, steps, src_elem, src_lam, f0, ts, rec_elem, rec_lam, t0=0.0):
+        """Independent shots, each with its own point source (src_elem[s] = -1:
+        none), sharing the receivers.  q0: (S, 4, K, Np).  Returns the final
+        states (S, 4, K, Np) and the traces (steps, S, R): the pressure at the
+        receivers after every step."""
+        q0 = np.asarray(q0, dtype=np.float64)
+        S, R = q0.shape[0], len(rec_elem)
+        W = self.receiver_weights(rec_lam) if R else np.zeros((0, self.Np))
+        traces = np.zeros((steps, S, R))
+        out = np.empty_like(q0)
+        for s in range(S):
+            forcing = None if src_elem[s] < 0 else self.point_source(src_elem[s], src_lam[s], f0, ts)
+
+            def record(n, q, s=s):
+                for r in range(R):
+                    traces[n - 1, s, r] = q[0, rec_elem[r]] @ W[r]
+            out[s] = self.lsrk4(q0[s], dt, steps, callback=record, forcing=forcing, t0=t0)
+        return out, traces
+
+    def pressure_integral(self, q):
+        """sum_k int_{D^k} p / kappa: advanced only by the source term (the
+        upwind flux telescopes across interior faces and vanishes on rigid
+        walls), so under a point source its rate is w(t)."""
+        m = bb.mass(self.N)
+        return float(np.sum(self.geo.volume * (q[0] @ m.sum(axis=1)) / self.kappa))
 
     # -- diagnostics -----------------------------------------------------------
     def energy(self, q):
@@ -189,6 +267,12 @@ class Problem:
 # ---------------------------------------------------------------------------
 # quadrature, projection and errors
 # ---------------------------------------------------------------------------
+
+def ricker(t, f0, ts):
+    """Ricker wavelet (1 - 2 pi^2 f0^2 (t - ts)^2) exp(-pi^2 f0^2 (t - ts)^2)."""
+    a = (np.pi * f0 * (t - ts)) ** 2
+    return (1.0 - 2.0 * a) * np.exp(-a)
+
 
 def tet_quadrature(n):
     """Collapsed-coordinate Gauss-Jacobi rule on the unit simplex, exact for

@@ -7,10 +7,12 @@ streams only.
 """
 from ._lib import (BBDG_BC_PRESSURE_RELEASE, BBDG_BC_RIGID, BBDG_F32, BBDG_F64,
                    BBDG_RHS_FULL, BBDG_RHS_SURFACE, BBDG_RHS_VOLUME, BBDGError, load)
-from .solver import MeshData, Solver, alpha_table, mesh_geometry, nodal_operators, np_count
+from .solver import (BatchedSolver, MeshData, Solver, alpha_table, bernstein_eval, locate_points,
+                     mesh_geometry, nodal_operators, np_count)
 
 __all__ = [
-    "Solver", "MeshData", "alpha_table", "mesh_geometry", "nodal_operators", "np_count", "load", "BBDGError",
+    "Solver", "BatchedSolver", "MeshData", "alpha_table", "mesh_geometry", "nodal_operators", "np_count",
+    "locate_points", "bernstein_eval", "load", "BBDGError",
     "BBDG_F64", "BBDG_F32", "BBDG_BC_RIGID", "BBDG_BC_PRESSURE_RELEASE",
     "BBDG_RHS_FULL", "BBDG_RHS_VOLUME", "BBDG_RHS_SURFACE",
 ]

@@ -17,7 +17,7 @@ BBDG_RHS_FULL, BBDG_RHS_VOLUME, BBDG_RHS_SURFACE = 0, 1, 2
 ERRORS = {
     0: "BBDG_OK", -1: "BBDG_E_ARG", -2: "BBDG_E_ORDER", -3: "BBDG_E_MESH",
     -4: "BBDG_E_NONFINITE", -5: "BBDG_E_DTYPE", -6: "BBDG_E_BC", -7: "BBDG_E_DEVICE",
-    -8: "BBDG_E_LAUNCH", -9: "BBDG_E_MODE",
+    -8: "BBDG_E_LAUNCH", -9: "BBDG_E_MODE", -10: "BBDG_E_OUTSIDE", -11: "BBDG_E_RESIDENT",
 }
 
 # name -> (restype, argtypes)
@@ -41,6 +41,17 @@ SIGNATURES = {
     "bbdg_work_bytes": (_c.c_size_t, [_c.c_void_p]),
     "bbdg_run": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_double, _c.c_double,
                             _c.c_int64, _c.c_void_p]),
+    "bbdg_locate_points": (_c.c_int, [_c.c_int64, _c.c_int64, _c.c_void_p, _c.c_void_p, _c.c_int64,
+                                      _c.c_void_p, _c.c_void_p, _c.c_void_p]),
+    "bbdg_bernstein_eval": (_c.c_int, [_c.c_int, _c.c_int64, _c.c_void_p, _c.c_void_p]),
+    "bbdg_source_coeffs": (_c.c_int, [_c.c_void_p, _c.c_int64, _c.c_void_p, _c.c_void_p, _c.c_void_p]),
+    "bbdg_batched_work_bytes": (_c.c_size_t, [_c.c_void_p, _c.c_int64]),
+    "bbdg_run_batched": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_int64, _c.c_void_p, _c.c_void_p,
+                                    _c.c_double, _c.c_double, _c.c_int, _c.c_void_p, _c.c_void_p,
+                                    _c.c_void_p, _c.c_void_p, _c.c_double, _c.c_double, _c.c_int64,
+                                    _c.c_int, _c.c_void_p]),
+    "bbdg_tune_batched": (_c.c_int, [_c.c_void_p, _c.c_int64, _c.c_void_p, _c.POINTER(_c.c_int),
+                                     _c.c_void_p]),
     "bbdg_copy_probe": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_size_t, _c.c_void_p]),
     "bbdg_destroy": (_c.c_int, [_c.c_void_p]),
     "bbdg_strerror": (_c.c_char_p, [_c.c_int]),

@@ -21,10 +21,30 @@ struct StageArgs {
   T rk_a, rk_b, dt;
   int read_res;
   int bc;
+  // Batched multi-stage launches (mode kBatched): S shots stored shot-major
+  // (S, 4, K, Np); stage s reads buffer s % 2 of {qout, qalt} and writes the
+  // other; a Ricker point source per shot is added to the pressure equation;
+  // receivers sample the pressure after every fifth stage.
+  int64_t shots;
+  T* qalt;
+  int64_t nstages;
+  double t0, dtd;           // start time and step of the wavelet clock
+  const int32_t* src_elem;  // S: source element of each shot (-1: none)
+  const T* src_coef;        // S x Np: kappa (M^k)^{-1} B(lambda_s)
+  double f0, tshift;        // Ricker peak frequency and delay
+  int R;                    // receivers per shot
+  const int32_t* rec_elem;  // R
+  const T* rec_coef;        // R x Np: B_alpha(lambda_r)
+  T* traces;                // steps x S x R
 };
 
 template <typename T>
 hipError_t launch_stage(int N, int mode, const StageArgs<T>& a, hipStream_t stream);
+
+// Persistent cooperative launch of a whole batched run; wpb = waves per
+// workgroup (1, 2 or 4).  Fails (no launch) when the grid cannot be co-resident.
+template <typename T>
+hipError_t launch_batched(int N, int wpb, const StageArgs<T>& a, hipStream_t stream);
 
 // Arguments of the dense nodal comparator stage kernel: the same fields,
 // geometry and connectivity plus the dense operators

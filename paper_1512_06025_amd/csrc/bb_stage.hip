@@ -40,6 +40,7 @@
 //   LSRK4 update (fused): res = a res + dt rhs, q_out = q + b res.
 // Fields ping-pong between q_in and q_out, so no stage overwrites a trace
 // that another wave still reads.
+#include <hip/hip_cooperative_groups.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -64,7 +65,6 @@ struct Shape {
   // faces per lift batch (bounds the LDS of the face vectors)
   static constexpr int FB = sizeof(T) == 8 ? (N >= 8 ? 1 : (N >= 6 ? 2 : 4)) : (N >= 8 ? 2 : 4);
   static constexpr int NV = 2 * FB;
-  static constexpr int WPB = 4;
   static constexpr int HG = E * kGeoStride;               // header doubles per wave
   static constexpr int NHG = (HG + 63) / 64;
   static constexpr int NHE = (E * 4 + 63) / 64;
@@ -133,12 +133,30 @@ __device__ __forceinline__ void st(T* base, uint32_t idx, T x) {
   *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + (idx * (uint32_t)sizeof(T))) = x;
 }
 
-template <int N, typename T, int MODE>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Occ<N, T>::value)))
+// Carpenter-Kennedy (5,4) 2N-storage coefficients (batched runs step inside
+// the kernel): res = a_s res + dt rhs(t + c_s dt), q += b_s res.
+__constant__ double kLsrkA[5] = {0.0, -567301805773.0 / 1357537059087.0, -2404267990393.0 / 2016746695238.0,
+                                 -3550918686646.0 / 2091501179385.0, -1275806237668.0 / 842570457699.0};
+__constant__ double kLsrkB[5] = {1432997174477.0 / 9575080441755.0, 5161836677717.0 / 13612068292357.0,
+                                 1720146321549.0 / 2090206949498.0, 3134564353537.0 / 4481467310338.0,
+                                 2277821191437.0 / 14882151754819.0};
+__constant__ double kLsrkC[5] = {0.0, 1432997174477.0 / 9575080441755.0, 2526269341429.0 / 6820363962896.0,
+                                 2006345519317.0 / 3224310063776.0, 2802321613138.0 / 2924317926251.0};
+
+// Ricker wavelet (1 - 2 pi^2 f0^2 s^2) exp(-pi^2 f0^2 s^2), s = t - tshift.
+__device__ __forceinline__ double ricker(double t, double f0, double tshift) {
+  const double a = 3.14159265358979323846 * f0 * (t - tshift);
+  return (1.0 - 2.0 * a * a) * exp(-a * a);
+}
+
+template <int N, typename T, int MODE, int WPB>
+__global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(Occ<N, T>::value)))
 void bb_stage_kernel(StageArgs<T> A) {
   using S = Shape<N, T>;
   constexpr int Np = S::Np, Nfp = S::Nfp, E = S::E, NPL = S::NPL, NFI = S::NFI;
-  constexpr int FB = S::FB, NV = S::NV, WPB = S::WPB, GEO = S::GEO;
+  constexpr int FB = S::FB, NV = S::NV, GEO = S::GEO;
+  constexpr bool kBatch = (MODE == kBatched);
+  constexpr bool kUpdate = (MODE == kStage || MODE == kBatched);
   constexpr int PK = sizeof(T) == 4 ? 4 : 1;
   constexpr bool kVol = (MODE != kRhsSurface);
   constexpr bool kSurf = (MODE != kRhsVolume);
@@ -217,22 +235,39 @@ void bb_stage_kernel(StageArgs<T> A) {
   __syncthreads();
 
   const int lane0 = tid & 63;
-  const int w = tid >> 6;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave index (uniform)
   const int64_t K = A.K;
   const int64_t KNp = K * Np;
-  const T* qin_f[4] = {A.qin, A.qin + KNp, A.qin + 2 * KNp, A.qin + 3 * KNp};
-  const int64_t G = (K + E - 1) / E;
+  const int64_t G = (K + E - 1) / E;  // element groups per shot
+  const int64_t GS = G * (kBatch ? A.shots : 1);
   // XCD-aware split of the element groups (gridDim.x is a multiple of 8)
   const int xcd = blockIdx.x & 7;
-  const int64_t g_lo = G * xcd / 8, g_hi = G * (xcd + 1) / 8;
+  const int64_t g_lo = GS * xcd / 8, g_hi = GS * (xcd + 1) / 8;
   const int64_t wstride = (int64_t)(gridDim.x >> 3) * WPB;
-  int64_t g = g_lo + (int64_t)(blockIdx.x >> 3) * WPB + w;
+  const int64_t nst = kBatch ? A.nstages : 1;
 
+  for (int64_t stage = 0; stage < nst; ++stage) {
+  // stage constants: buffers, LSRK coefficients, source amplitude
+  const int s5 = (int)(stage % 5);
+  const T* qin_b = kBatch ? ((stage & 1) ? A.qalt : A.qout) : A.qin;
+  T* qout_b = kBatch ? ((stage & 1) ? A.qout : A.qalt) : A.qout;
+  const T rk_a = kBatch ? (T)kLsrkA[s5] : A.rk_a;
+  const T rk_b = kBatch ? (T)kLsrkB[s5] : A.rk_b;
+  const int read_res = kBatch ? (s5 != 0) : A.read_res;
+  const T amp = kBatch ? (T)ricker(A.t0 + (double)(stage / 5) * A.dtd + kLsrkC[s5] * A.dtd, A.f0, A.tshift) : (T)0;
+
+  int64_t g = g_lo + (int64_t)(blockIdx.x >> 3) * WPB + w;
   Header<N, T> hd;
-  if (g < g_hi) load_header<N, T>(hd, A, g, lane0);
+  // group g = shot * G + element group (shots * G < 2^32 is checked on the host)
+  if (g < g_hi) load_header<N, T>(hd, A, kBatch ? (int64_t)((uint32_t)g % (uint32_t)G) : g, lane0);
 
   for (; g < g_hi; g += wstride) {
-    const int64_t e0 = g * E;
+    const int64_t shot = kBatch ? (int64_t)((uint32_t)g / (uint32_t)G) : 0;
+    const int64_t e0 = (g - shot * G) * E;
+    const int64_t sb = shot * 4 * KNp;  // this shot's fields
+    const T* qin_f[4] = {qin_b + sb, qin_b + sb + KNp, qin_b + sb + 2 * KNp, qin_b + sb + 3 * KNp};
+    T* const res_s = A.res + (kUpdate ? sb : 0);
+    T* const qout_s = qout_b + sb;
     // Lane-derived addresses are cheap to recompute; hiding the lane id from
     // loop-invariant code motion keeps them from being hoisted out of the
     // element loop and occupying (or spilling) registers for its whole life.
@@ -268,9 +303,9 @@ void bb_stage_kernel(StageArgs<T> A) {
       noff[r] = ok ? (uint32_t)((e0 + el) * Np + n) : 0u;
 #pragma unroll
       for (int f = 0; f < 4; ++f) qv[r][f] = ld(qin_f[f], noff[r]);
-      if (MODE == kStage && A.read_res) {
+      if (kUpdate && read_res) {
 #pragma unroll
-        for (int f = 0; f < 4; ++f) rv[r][f] = ld(A.res + f * KNp, noff[r]);
+        for (int f = 0; f < 4; ++f) rv[r][f] = ld(res_s + f * KNp, noff[r]);
       } else {
 #pragma unroll
         for (int f = 0; f < 4; ++f) rv[r][f] = 0;
@@ -296,7 +331,8 @@ void bb_stage_kernel(StageArgs<T> A) {
       }
     }
     // ---- prefetch the next group's header -----------------------------------
-    if (g + wstride < g_hi) load_header<N, T>(hd, A, g + wstride, lane);
+    if (g + wstride < g_hi)
+      load_header<N, T>(hd, A, kBatch ? (int64_t)((uint32_t)(g + wstride) % (uint32_t)G) : g + wstride, lane);
 
     // ---- per-element derived geometry (one lane per element face) ------------
     for (int v = lane; v < E * 4; v += 64) {
@@ -503,6 +539,17 @@ void bb_stage_kernel(StageArgs<T> A) {
       }
     }
 
+    // ---- point source of this shot (pressure equation) -------------------------------
+    if constexpr (kBatch) {
+      const int32_t se = A.src_elem ? A.src_elem[shot] : -1;
+#pragma unroll
+      for (int r = 0; r < NPL; ++r) {
+        const int v = lane + 64 * r;
+        const int el = v / Np;
+        if (v < E * Np && e0 + el == se) rhs[r][0] += amp * A.src_coef[shot * Np + (v - el * Np)];
+      }
+    }
+
     // ---- update / store -------------------------------------------------------------
 #pragma unroll
     for (int r = 0; r < NPL; ++r) {
@@ -510,26 +557,48 @@ void bb_stage_kernel(StageArgs<T> A) {
       const int el = v / Np;
       if (v >= E * Np || e0 + el >= K) continue;
       const uint32_t off = noff[r];
-      if constexpr (MODE == kStage) {
+      if constexpr (kUpdate) {
+        const T dt = kBatch ? (T)A.dtd : A.dt;
 #pragma unroll
         for (int f = 0; f < 4; ++f) {
-          const T rs = A.dt * rhs[r][f] + A.rk_a * rv[r][f];
-          st(A.res + f * KNp, off, rs);
-          st(A.qout + f * KNp, off, qv[r][f] + A.rk_b * rs);
+          const T rs = dt * rhs[r][f] + rk_a * rv[r][f];
+          st(res_s + f * KNp, off, rs);
+          st(qout_s + f * KNp, off, qv[r][f] + rk_b * rs);
         }
       } else {
 #pragma unroll
-        for (int f = 0; f < 4; ++f) st(A.qout + f * KNp, off, rhs[r][f]);
+        for (int f = 0; f < 4; ++f) st(qout_s + f * KNp, off, rhs[r][f]);
+      }
+    }
+  }  // element groups
+
+  if constexpr (kBatch) {
+    cooperative_groups::this_grid().sync();
+    // receivers read the pressure after the fifth stage of each step
+    if (s5 == 4 && A.R > 0) {
+      const int64_t items = A.shots * A.R;
+      const int64_t step = stage / 5;
+      for (int64_t it = (int64_t)blockIdx.x * (64 * WPB) + tid; it < items; it += (int64_t)gridDim.x * 64 * WPB) {
+        const int64_t sh = it / A.R;
+        const int rr = (int)(it - sh * A.R);
+        const int32_t re = A.rec_elem[rr];
+        T acc = (T)NAN;
+        if (re >= 0 && re < K) {
+          const T* pr = qout_b + sh * 4 * KNp + (int64_t)re * Np;
+          const T* cr = A.rec_coef + (int64_t)rr * Np;
+          acc = 0;
+#pragma unroll 8
+          for (int n = 0; n < Np; ++n) acc += cr[n] * pr[n];
+        }
+        A.traces[(step * A.shots + sh) * A.R + rr] = acc;
       }
     }
   }
+  }  // stages
 }
 
-template <int N, typename T, int MODE>
-static hipError_t launch_one(const StageArgs<T>& a, hipStream_t stream) {
-  using S = Shape<N, T>;
-  const int64_t groups = (a.K + S::E - 1) / S::E;
-  if (groups <= 0) return hipSuccess;
+template <int N, typename T, int MODE, int WPB>
+static hipError_t resident_grid(int64_t groups, int64_t* grid_out) {
   static int resident = 0;  // co-resident workgroups per CU for this instantiation
   static int cus = 0;
   if (resident == 0) {
@@ -537,18 +606,72 @@ static hipError_t launch_one(const StageArgs<T>& a, hipStream_t stream) {
     if (hipGetDevice(&dev) != hipSuccess) return hipErrorInvalidDevice;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return hipErrorInvalidDevice;
     int occ = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, bb_stage_kernel<N, T, MODE>, 64 * S::WPB, 0) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, bb_stage_kernel<N, T, MODE, WPB>, 64 * WPB, 0) != hipSuccess)
       return hipErrorInvalidValue;
-    resident = occ > 0 ? occ : 1;
+    if (occ < 1) return hipErrorInvalidConfiguration;
+    resident = occ;
   }
-  const int64_t needed = (groups + S::WPB - 1) / S::WPB;
+  const int64_t needed = (groups + WPB - 1) / WPB;
   int64_t grid = (int64_t)resident * cus;
   if (grid > ((needed + 7) / 8) * 8) grid = ((needed + 7) / 8) * 8;
-  grid = ((grid + 7) / 8) * 8;
-  if (grid < 8) grid = 8;
-  hipLaunchKernelGGL((bb_stage_kernel<N, T, MODE>), dim3((unsigned)grid), dim3(64 * S::WPB), 0, stream, a);
+  if (MODE == kBatched) grid = grid / 8 * 8;  // stay within the co-resident bound
+  else grid = ((grid + 7) / 8) * 8;
+  if (grid < 8) return MODE == kBatched ? hipErrorCooperativeLaunchTooLarge : (*grid_out = 8, hipSuccess);
+  *grid_out = grid;
+  return hipSuccess;
+}
+
+template <int N, typename T, int MODE>
+static hipError_t launch_one(const StageArgs<T>& a, hipStream_t stream) {
+  using S = Shape<N, T>;
+  const int64_t groups = (a.K + S::E - 1) / S::E;
+  if (groups <= 0) return hipSuccess;
+  int64_t grid = 0;
+  const hipError_t e = resident_grid<N, T, MODE, 4>(groups, &grid);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((bb_stage_kernel<N, T, MODE, 4>), dim3((unsigned)grid), dim3(256), 0, stream, a);
   return hipGetLastError();
 }
+
+template <int N, typename T, int WPB>
+static hipError_t launch_batched_one(const StageArgs<T>& a, hipStream_t stream) {
+  using S = Shape<N, T>;
+  const int64_t groups = (a.K + S::E - 1) / S::E * a.shots;
+  if (groups <= 0 || a.nstages <= 0) return hipSuccess;
+  int64_t grid = 0;
+  const hipError_t e = resident_grid<N, T, kBatched, WPB>(groups, &grid);
+  if (e != hipSuccess) return e;
+  StageArgs<T> args = a;
+  void* params[] = {&args};
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(bb_stage_kernel<N, T, kBatched, WPB>),
+                                    dim3((unsigned)grid), dim3(64 * WPB), params, 0, stream);
+}
+
+template <typename T>
+hipError_t launch_batched(int N, int wpb, const StageArgs<T>& a, hipStream_t stream) {
+#define BBDG_BATCH_CASE(NN)                                       \
+  case NN:                                                        \
+    if (wpb == 1) return launch_batched_one<NN, T, 1>(a, stream); \
+    if (wpb == 2) return launch_batched_one<NN, T, 2>(a, stream); \
+    if (wpb == 4) return launch_batched_one<NN, T, 4>(a, stream); \
+    return hipErrorInvalidValue;
+  switch (N) {
+    BBDG_BATCH_CASE(1)
+    BBDG_BATCH_CASE(2)
+    BBDG_BATCH_CASE(3)
+    BBDG_BATCH_CASE(4)
+    BBDG_BATCH_CASE(5)
+    BBDG_BATCH_CASE(6)
+    BBDG_BATCH_CASE(7)
+    BBDG_BATCH_CASE(8)
+    BBDG_BATCH_CASE(9)
+    default: return hipErrorInvalidValue;
+  }
+#undef BBDG_BATCH_CASE
+}
+
+template hipError_t launch_batched<double>(int, int, const StageArgs<double>&, hipStream_t);
+template hipError_t launch_batched<float>(int, int, const StageArgs<float>&, hipStream_t);
 
 template <typename T, int MODE>
 static hipError_t launch_mode(int N, const StageArgs<T>& a, hipStream_t stream) {

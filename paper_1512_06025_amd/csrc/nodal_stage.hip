@@ -14,8 +14,9 @@
 // surface term one MFMA GEMM (NpP x Kl) x (Kl x 16) on the face-node fluxes
 // (the p flux and the velocity flux scaled by the three components of g_f),
 // followed by the fused LSRK4 update.  MFMA tiles are 16 x 16 x 4
-// (v_mfma_f64_16x16x4f64 / v_mfma_f32_16x16x4f32); lane l holds A[l%16][l/16],
-// B[l/16][l%16] and D[4(l/16)+r][l%16], r = 0..3.
+// (v_mfma_f64_16x16x4f64 / v_mfma_f32_16x16x4f32); lane l holds A[l%16][l/16]
+// and B[l/16][l%16]; accumulator register r of lane l is D[row][l%16] with
+// row = l/16 + 4r for the FP64 instruction and 4(l/16) + r for the FP32 one.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -44,6 +45,7 @@ struct Mfma<double> {
   static __device__ __forceinline__ acc mac(double a, double b, acc c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
+  static __device__ __forceinline__ int row(int kq, int r) { return kq + 4 * r; }
 };
 template <>
 struct Mfma<float> {
@@ -52,6 +54,7 @@ struct Mfma<float> {
   static __device__ __forceinline__ acc mac(float a, float b, acc c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
+  static __device__ __forceinline__ int row(int kq, int r) { return 4 * kq + r; }
 };
 
 }  // namespace
@@ -165,7 +168,7 @@ __global__ __launch_bounds__((64 * NodalWaves<N, T>::value)) void nodal_stage_ke
             c = M::mac(a, b, c);
           }
 #pragma unroll
-          for (int rr = 0; rr < 4; ++rr) ys[(mt * 16 + 4 * kq + rr) * NC + ri] = c[rr];
+          for (int rr = 0; rr < 4; ++rr) ys[(mt * 16 + M::row(kq, rr)) * NC + ri] = c[rr];
         }
         wave_sync_lds();
 #pragma unroll
@@ -244,7 +247,7 @@ __global__ __launch_bounds__((64 * NodalWaves<N, T>::value)) void nodal_stage_ke
           c = M::mac(a, b, c);
         }
 #pragma unroll
-        for (int rr = 0; rr < 4; ++rr) xs[(mt * 16 + 4 * kq + rr) * NC + ri] = c[rr];
+        for (int rr = 0; rr < 4; ++rr) xs[(mt * 16 + M::row(kq, rr)) * NC + ri] = c[rr];
       }
       wave_sync_lds();
 #pragma unroll

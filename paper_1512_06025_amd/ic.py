@@ -23,6 +23,14 @@ def _vandermonde(N):
     return lam, V
 
 
+def lattice_values(N, VX, EToV, func):
+    """(K, Np) values of func at the lattice points (control-point positions)."""
+    lam, _ = _vandermonde(N)
+    X = np.asarray(VX, dtype=np.float64)[np.asarray(EToV)]
+    pts = np.einsum("pi,kid->kpd", lam, X)
+    return func(pts[..., 0], pts[..., 1], pts[..., 2])
+
+
 def interpolate(N, VX, EToV, func):
     """(K, Np) Bernstein coefficients interpolating func(x, y, z) on each element."""
     lam, V = _vandermonde(N)
@@ -32,9 +40,10 @@ def interpolate(N, VX, EToV, func):
     return np.linalg.solve(V, vals.T).T
 
 
-def initial_state(N, VX, EToV, p0):
-    """(4, K, Np) float64 state with p interpolated from p0 and zero velocity."""
+def initial_state(N, VX, EToV, p0, basis="bb"):
+    """(4, K, Np) float64 state with p interpolated from p0 and zero velocity:
+    Bernstein coefficients (basis="bb") or lattice values (basis="nodal")."""
     K = np.asarray(EToV).shape[0]
     q = np.zeros((4, K, alpha_table(N).shape[0]))
-    q[0] = interpolate(N, VX, EToV, p0)
+    q[0] = interpolate(N, VX, EToV, p0) if basis == "bb" else lattice_values(N, VX, EToV, p0)
     return q

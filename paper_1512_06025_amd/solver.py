@@ -21,10 +21,12 @@ def alpha_table(N):
 
 
 class MeshData:
-    """Geometry and connectivity computed by bbdg_mesh_geometry (host arrays)."""
+    """Geometry and connectivity computed by bbdg_mesh_geometry (host arrays),
+    with the vertex coordinates and element vertices it came from."""
 
-    def __init__(self, geo, EToE, EToF, EToO):
+    def __init__(self, geo, EToE, EToF, EToO, VX=None, EToV=None):
         self.geo, self.EToE, self.EToF, self.EToO = geo, EToE, EToF, EToO
+        self.VX, self.EToV = VX, EToV
         self.K = geo.shape[0]
 
 
@@ -39,7 +41,29 @@ def mesh_geometry(VX, EToV):
     check(load().bbdg_mesh_geometry(K, Nv, VX.ctypes.data, EToV.ctypes.data, geo.ctypes.data,
                                     EToE.ctypes.data, EToF.ctypes.data, EToO.ctypes.data),
           "bbdg_mesh_geometry")
-    return MeshData(geo, EToE, EToF, EToO)
+    return MeshData(geo, EToE, EToF, EToO, VX, EToV)
+
+
+def locate_points(mesh, xyz):
+    """(elem (n,) int32, bary (n, 4)) of points xyz (n, 3); raises if a point
+    lies outside the mesh."""
+    xyz = np.ascontiguousarray(np.atleast_2d(xyz), dtype=np.float64)
+    n = xyz.shape[0]
+    elem = np.zeros(n, dtype=np.int32)
+    bary = np.zeros((n, 4))
+    check(load().bbdg_locate_points(mesh.K, mesh.VX.shape[0], mesh.VX.ctypes.data, mesh.EToV.ctypes.data,
+                                    n, xyz.ctypes.data, elem.ctypes.data, bary.ctypes.data),
+          "bbdg_locate_points")
+    return elem, bary
+
+
+def bernstein_eval(N, bary):
+    """(n, Np) Bernstein polynomials of order N at barycentric points (n, 4)."""
+    bary = np.ascontiguousarray(np.atleast_2d(bary), dtype=np.float64)
+    out = np.zeros((bary.shape[0], np_count(N)))
+    check(load().bbdg_bernstein_eval(int(N), bary.shape[0], bary.ctypes.data, out.ctypes.data),
+          "bbdg_bernstein_eval")
+    return out
 
 
 def _stream_ptr(stream):
@@ -131,3 +155,92 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+
+class BatchedSolver:
+    """Independent shots on one mesh and wavespeed, advanced together in one
+    persistent kernel launch per run.
+
+    sources: (S, 3) source positions (one Ricker point source per shot) or
+    None; receivers: (R, 3) positions shared by all shots.  States are CUDA
+    tensors (S, 4, K, Np); run() returns the receiver traces (steps, S, R).
+    wpb = 0 lets bbdg_tune_batched pick the waves per workgroup on first use."""
+
+    def __init__(self, N, mesh, c, shots, sources=None, receivers=None, f0=8.0, ts=0.125,
+                 dtype="f32", bc="rigid", device=0, wpb=0):
+        import torch
+        self.solver = Solver(N, mesh, c, dtype=dtype, bc=bc, device=device)
+        s = self.solver
+        self.S = int(shots)
+        self.f0, self.ts = float(f0), float(ts)
+        self.wpb = int(wpb)
+        dev = s.device
+        self.src_elem = self.src_coef = None
+        if sources is not None:
+            elem, bary = locate_points(mesh, sources)
+            if elem.shape[0] != self.S:
+                raise ValueError("need one source per shot")
+            coef = np.zeros((self.S, s.Np))
+            check(load().bbdg_source_coeffs(s._h, self.S, elem.ctypes.data, bary.ctypes.data, coef.ctypes.data),
+                  "bbdg_source_coeffs")
+            self.src_elem = torch.from_numpy(elem).to(dev)
+            self.src_coef = torch.from_numpy(coef).to(dev, s.torch_dtype)
+        self.R = 0
+        self.rec_elem = self.rec_coef = None
+        if receivers is not None and len(receivers):
+            elem, bary = locate_points(mesh, receivers)
+            self.R = elem.shape[0]
+            self.rec_elem = torch.from_numpy(elem).to(dev)
+            self.rec_coef = torch.from_numpy(bernstein_eval(N, bary)).to(dev, s.torch_dtype)
+        self._work = None
+
+    def empty_state(self):
+        import torch
+        s = self.solver
+        return torch.zeros((self.S, 4, s.K, s.Np), dtype=s.torch_dtype, device=s.device)
+
+    def _buffer(self, nbytes):
+        import torch
+        return torch.empty(nbytes // 8 + 32, dtype=torch.float64, device=self.solver.device)
+
+    def work(self):
+        if self._work is None:
+            self._work = self._buffer(load().bbdg_batched_work_bytes(self.solver._h, self.S))
+        return self._work
+
+    def tune(self, stream=None):
+        """Times the launch shapes and keeps the fastest; returns waves per workgroup."""
+        s = self.solver
+        state = self.S * 4 * s.K * s.Np * (8 if s.dtype == "f64" else 4)
+        scratch = self._buffer(load().bbdg_batched_work_bytes(s._h, self.S) + state + 256)
+        out = ctypes.c_int(0)
+        check(load().bbdg_tune_batched(s._h, self.S, ctypes.c_void_p(scratch.data_ptr()), ctypes.byref(out),
+                                       _stream_ptr(stream)), "bbdg_tune_batched")
+        del scratch
+        self.wpb = out.value
+        return self.wpb
+
+    def run(self, q, dt, steps, t0=0.0, traces=None, stream=None):
+        """Advance every shot of q in place; returns the traces (steps, S, R)."""
+        import torch
+        s = self.solver
+        if not (isinstance(q, torch.Tensor) and q.is_cuda and q.dtype == s.torch_dtype and q.is_contiguous()
+                and tuple(q.shape) == (self.S, 4, s.K, s.Np)):
+            raise ValueError("expected a contiguous CUDA tensor (%d, 4, %d, %d) of %s"
+                             % (self.S, s.K, s.Np, s.torch_dtype))
+        if self.wpb == 0:
+            self.tune(stream)
+        if traces is None:
+            traces = torch.empty((int(steps), self.S, self.R), dtype=s.torch_dtype, device=s.device)
+        w = self.work()
+
+        def ptr(t):
+            return ctypes.c_void_p(t.data_ptr() if t is not None else None)
+        check(load().bbdg_run_batched(s._h, ptr(q), self.S, ptr(self.src_elem), ptr(self.src_coef),
+                                      self.f0, self.ts, self.R, ptr(self.rec_elem), ptr(self.rec_coef),
+                                      ptr(traces) if self.R else ctypes.c_void_p(None), ptr(w), float(t0),
+                                      float(dt), int(steps), self.wpb, _stream_ptr(stream)), "bbdg_run_batched")
+        return traces
+
+    def close(self):
+        self.solver.close()

@@ -151,3 +151,40 @@ def test_null_handles_and_strerror(lib):
     for code in list(_lib.ERRORS):
         assert lib.bbdg_strerror(code)
     assert lib.bbdg_strerror(-99) == b"unknown error code"
+    assert lib.bbdg_run_batched(None, None, 1, None, None, 8.0, 0.1, 0, None, None, None, None,
+                                0.0, 1e-3, 1, 0, None) == -1
+    assert lib.bbdg_tune_batched(None, 1, None, None, None) == -1
+    assert lib.bbdg_batched_work_bytes(None, 4) == 0
+    assert lib.bbdg_source_coeffs(None, 0, None, None, None) == -1
+
+
+# -- host utilities of the batched path (no device involved) ---------------------
+
+def test_locate_points_matches_oracle():
+    from oracle import dg
+    VX, EToV = workload.kuhn_cube_mesh(3, 0.1, drop_last=7)
+    mesh = P.mesh_geometry(VX, EToV)
+    prob = dg.Problem(VX, EToV, 2, np.ones(EToV.shape[0]))
+    rng = np.random.default_rng(21)
+    pts = rng.uniform(0.0, 1.0, (200, 3))
+    oe, ol = prob.locate(pts)
+    inside = oe >= 0
+    e, l = P.locate_points(mesh, pts[inside])
+    np.testing.assert_array_equal(e, oe[inside])
+    np.testing.assert_allclose(l, ol[inside], atol=1e-13)
+    # a point in the removed elements (or outside the cube) is an error
+    if not inside.all():
+        with pytest.raises(_lib.BBDGError):
+            P.locate_points(mesh, pts)
+    with pytest.raises(_lib.BBDGError):
+        P.locate_points(mesh, [[1.2, 0.5, 0.5]])
+
+
+@pytest.mark.parametrize("N", [1, 4, 9])
+def test_bernstein_eval_matches_oracle(N):
+    from oracle import dg
+    rng = np.random.default_rng(N)
+    lam = rng.dirichlet(np.ones(4), size=30)
+    np.testing.assert_allclose(P.bernstein_eval(N, lam), dg.bernstein_eval(N, lam), rtol=1e-13, atol=1e-15)
+    # partition of unity
+    np.testing.assert_allclose(P.bernstein_eval(N, lam).sum(axis=1), 1.0, rtol=1e-14)

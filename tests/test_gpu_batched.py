@@ -1,0 +1,153 @@
+"""Batched shots (one persistent cooperative launch) against the FP64 oracle.
+
+Each shot is an independent forward run with its own Ricker point source;
+all shots share the receivers.  Final states and receiver traces are
+compared with the oracle's per-shot runs (relative L2 1e-12 in FP64, 1e-5 in
+FP32); source and receiver element ids must match exactly.
+"""
+import numpy as np
+import pytest
+
+import workload
+from oracle import dg
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-12, "f32": 1e-5}
+F0, TS = 8.0, 0.125
+
+
+def _rel(a, b):
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+def _host(x):
+    torch.cuda.synchronize()
+    return x.detach().to("cpu", torch.float64).numpy()
+
+
+def _case(N, n=2, drop_last=5, shots=4, nrec=5, seed=3):
+    import paper_1512_06025_amd as P
+    VX, EToV = workload.kuhn_cube_mesh(n, 0.1, drop_last=drop_last)
+    c = workload.wavespeed(EToV.shape[0], 1.0, 3.0)
+    mesh = P.mesh_geometry(VX, EToV)
+    prob = dg.Problem(VX, EToV, N, c)
+    rng = np.random.default_rng(seed)
+    # keep points inside the part of the cube that drop_last leaves meshed
+    src = rng.uniform(0.1, 0.45, (shots, 3))
+    rec = rng.uniform(0.1, 0.45, (nrec, 3))
+    return P, mesh, c, prob, src, rec
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("N", [1, 3, 4, 6])
+def test_batched_parity(N, dtype):
+    P, mesh, c, prob, src, rec = _case(N)
+    S, dt, steps, t0 = src.shape[0], 2e-3, 7, 0.08   # odd stage count: result in the second buffer
+    bs = P.BatchedSolver(N, mesh, c, S, sources=src, receivers=rec, f0=F0, ts=TS, dtype=dtype, wpb=4)
+    # shot S-1 has no source but a nonzero initial state
+    bs.src_elem[S - 1] = -1
+    q0 = np.zeros((S, 4, prob.K, prob.Np))
+    q0[S - 1] = workload.random_coeffs(prob.K, prob.Np, seed=77)
+    if dtype == "f32":
+        q0 = q0.astype(np.float32).astype(np.float64)
+    q = torch.from_numpy(q0).to("cuda", bs.solver.torch_dtype)
+    tr = bs.run(q, dt, steps, t0=t0)
+
+    se, sl = prob.locate(src)
+    re, rl = prob.locate(rec)
+    np.testing.assert_array_equal(_host(bs.src_elem)[:-1], se[:-1])
+    np.testing.assert_array_equal(_host(bs.rec_elem), re)
+    se[-1] = -1
+    want_q, want_tr = prob.run_shots(q0, dt, steps, se, sl, F0, TS, re, rl, t0=t0)
+    assert _rel(_host(q), want_q) < TOL[dtype]
+    for s in range(S):
+        assert _rel(_host(q)[s], want_q[s]) < TOL[dtype], s
+    assert tr.shape == (steps, S, len(rec))
+    assert _rel(_host(tr), want_tr) < TOL[dtype]
+    bs.close()
+
+
+def test_launch_shapes_agree_bitwise():
+    """Waves per workgroup change only the work distribution, not the arithmetic."""
+    P, mesh, c, prob, src, rec = _case(3, n=3, drop_last=0, shots=3)
+    outs = []
+    for wpb in (1, 2, 4):
+        bs = P.BatchedSolver(3, mesh, c, 3, sources=src, receivers=rec, dtype="f64", wpb=wpb)
+        q = bs.empty_state()
+        tr = bs.run(q, 1e-3, 4, t0=0.1)
+        outs.append((q.clone(), tr.clone()))
+        bs.close()
+    for q, tr in outs[1:]:
+        assert torch.equal(q, outs[0][0]) and torch.equal(tr, outs[0][1])
+
+
+def test_autotuner_picks_a_candidate():
+    P, mesh, c, prob, src, rec = _case(4, n=3, drop_last=0, shots=2)
+    bs = P.BatchedSolver(4, mesh, c, 2, sources=src, receivers=rec, dtype="f32")
+    assert bs.tune() in (1, 2, 4)
+    q = bs.empty_state()
+    tr = bs.run(q, 1e-3, 3, t0=0.1)
+    assert torch.isfinite(tr).all() and torch.isfinite(q).all()
+    bs.close()
+
+
+def test_source_coefficients_match_oracle():
+    from paper_1512_06025_amd import _lib
+    P, mesh, c, prob, src, rec = _case(5, shots=6)
+    s = P.Solver(5, mesh, c)
+    elem, bary = P.locate_points(mesh, src)
+    coef = np.zeros((len(elem), prob.Np))
+    _lib.check(_lib.load().bbdg_source_coeffs(s._h, len(elem), elem.ctypes.data, bary.ctypes.data,
+                                              coef.ctypes.data), "bbdg_source_coeffs")
+    oe, ol = prob.locate(src)
+    for i in range(len(elem)):
+        want = prob.point_source_vector(oe[i], ol[i])
+        np.testing.assert_allclose(coef[i], want, rtol=0, atol=1e-12 * np.abs(want).max())
+    s.close()
+
+
+def test_c4_full_size_sampled():
+    """The 64-shot, 24,576-tet, N = 4 FP32 workload in the launch configuration
+    the benchmark times (autotuned), two steps: the last shot (largest
+    offsets) re-run by the oracle, and for every shot the pressure integral,
+    which only the source changes, against the same LSRK quadrature of the
+    wavelet."""
+    import paper_1512_06025_amd as P
+    cfg, VX, EToV, c = workload.build_preset("c4")
+    mesh = P.mesh_geometry(VX, EToV)
+    S = cfg["shots"]
+    src = workload.source_positions(S)
+    rec = workload.receiver_grid()
+    bs = P.BatchedSolver(cfg["N"], mesh, c, S, sources=src, receivers=rec, f0=cfg["f0"], ts=cfg["ts"],
+                         dtype="f32")
+    bs.tune()
+    steps, t0, dt = 2, 0.1, cfg["dt"]
+    q = bs.empty_state()
+    tr = bs.run(q, dt, steps, t0=t0)
+    qh = _host(q)
+    prob = dg.Problem(VX, EToV, cfg["N"], c)
+    se, sl = prob.locate(src)
+    re, rl = prob.locate(rec)
+    for s in (S - 1,):
+        want, wtr = prob.run_shots(np.zeros((1, 4, prob.K, prob.Np)), dt, steps, se[s:s + 1], sl[s:s + 1],
+                                   cfg["f0"], cfg["ts"], re, rl, t0=t0)
+        assert _rel(qh[s], want[0]) < 1e-5, s
+        assert _rel(_host(tr)[:, s], wtr[:, 0]) < 1e-5, s
+    # conservation for every shot
+    I_res = 0.0
+    I = 0.0
+    for n in range(steps):
+        for st in range(5):
+            I_res = dg.LSRK_A[st] * I_res + dt * dg.ricker(t0 + n * dt + dg.LSRK_C[st] * dt, cfg["f0"], cfg["ts"])
+            I += dg.LSRK_B[st] * I_res
+    # FP32 rounding acts on every coefficient, so the bar scales with the sum
+    # of the magnitudes of the integral's terms (the source vector oscillates)
+    from oracle import bernstein as bb
+    msum = bb.mass(cfg["N"]).sum(axis=1)
+    for s in range(S):
+        got = prob.pressure_integral(qh[s])
+        scale = np.sum(np.abs(prob.geo.volume[:, None] * qh[s][0] * msum[None, :] / prob.kappa[:, None]))
+        assert abs(got - I) < 1e-5 * scale, (s, got, I, scale)
+    bs.close()

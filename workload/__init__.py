@@ -122,8 +122,10 @@ PRESETS = {
     "c2": dict(n=16, jitter=0.1, N=5, c=(1.0, 1.0), ic="standing_mode", steps=1000),
     # 196,608 tets, N in {1,3,5,7,9}, c ~ U[1,3], Gaussian pulse, 200 steps
     "c3": dict(n=32, jitter=0.0, N=5, c=(1.0, 3.0), ic="gaussian_pulse", steps=200),
-    # 24,576 tets, N=4, c ~ U[1,3], 64 shots, zero initial state, 500 steps
-    "c4": dict(n=16, jitter=0.0, N=4, c=(1.0, 3.0), ic="zero", steps=500, shots=64),
+    # 24,576 tets, N=4, c ~ U[1,3], 64 shots (Ricker point sources f0 = 8,
+    # delay 1/f0, seeded positions in [0.1, 0.9]^3), 8 x 8 receivers on
+    # z = 0.9, zero initial state, 500 steps
+    "c4": dict(n=16, jitter=0.0, N=4, c=(1.0, 3.0), ic="zero", steps=500, shots=64, f0=8.0, ts=0.125),
     # 24,576 tets, N=5, adjoint workload, 500 steps
     "c5": dict(n=16, jitter=0.0, N=5, c=(1.0, 1.0), ic="zero", steps=500),
 }
@@ -150,6 +152,18 @@ def build_preset(name, **overrides):
     return cfg, VX, EToV, c
 
 
+def source_positions(S, seed=SEED_SOURCES, lo=0.1, hi=0.9):
+    """(S, 3) point-source positions, uniform in [lo, hi]^3."""
+    return np.random.default_rng(seed).uniform(lo, hi, (S, 3))
+
+
+def receiver_grid(m=8, z=0.9, lo=0.1, hi=0.9):
+    """(m*m, 3) receivers on an m x m grid of the plane z, x and y in [lo, hi]."""
+    t = lo + (hi - lo) * np.arange(m) / (m - 1)
+    X, Y = np.meshgrid(t, t, indexing="ij")
+    return np.stack([X.ravel(), Y.ravel(), np.full(m * m, z)], axis=1)
+
+
 def element_count(n, drop_last=0):
     return 6 * n ** 3 - drop_last
 
@@ -157,5 +171,5 @@ def element_count(n, drop_last=0):
 __all__ = [
     "kuhn_cube_mesh", "wavespeed", "random_coeffs", "standing_mode_p0",
     "gaussian_pulse_p0", "INITIAL_FIELDS", "PRESETS", "preset", "build_preset",
-    "nodes_per_element", "element_count",
+    "nodes_per_element", "element_count", "source_positions", "receiver_grid",
 ]
