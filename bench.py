@@ -111,6 +111,44 @@ def time_batched(P, torch, workload, steps):
             "finite": finite}
 
 
+def time_gradient(P, torch, workload, steps):
+    """Misfit and its gradient in m = c^2: 8 shots on 24,576 tets, N = 5,
+    FP32 states (FP64 gradient sums), observations from the FP64 forward run
+    at a blob model, gradient at m = 1, checkpoints every 50 steps."""
+    cfg, VX, EToV, _ = workload.build_preset("c5")
+    N, K, S, dt = cfg["N"], cfg["K"], cfg["shots"], cfg["dt"]
+    mesh = P.mesh_geometry(VX, EToV)
+    src, rec = workload.plane_sources(S), workload.receiver_grid()
+    m_true = workload.blob_model(VX, EToV)
+    # observations: FP64 forward at m_true
+    obs_run = P.BatchedSolver(N, mesh, np.sqrt(m_true), S, sources=src, receivers=rec, f0=cfg["f0"], ts=cfg["ts"],
+                              dtype="f64", wpb=4)
+    d_obs = obs_run.run(obs_run.empty_state(), dt, steps)
+    obs_run.close()
+    mf = P.Misfit(N, mesh, np.ones(K), S, src, rec, d_obs, dt, steps, f0=cfg["f0"], ts=cfg["ts"],
+                  ckpt_every=cfg["ckpt_every"], dtype="f32")
+    mf.evaluate()
+    mf.gradient()  # warm-up
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    ev[0].record(stream)
+    J = mf.evaluate()
+    ev[1].record(stream)
+    g = mf.gradient()
+    ev[2].record(stream)
+    torch.cuda.synchronize()
+    t_fwd, t_adj = ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2])
+    finite = bool(torch.isfinite(g).all().item())
+    out = {"workload": "misfit gradient dJ/dm, %d shots (Ricker f0=%g on z=0.9), 64 receivers, %d^3x6 = %d tets, "
+                       "N=%d, FP32 states / FP64 sums, %d steps, checkpoints every %d" % (
+                           S, cfg["f0"], cfg["n"], K, N, steps, cfg["ckpt_every"]),
+           "J": float(J.item()), "forward_ms": t_fwd, "reverse_ms": t_adj,
+           "grad_over_forward": (t_fwd + t_adj) / t_fwd, "finite": finite}
+    mf.close()
+    return out
+
+
 def copy_probe(torch, P, nbytes=1 << 30, reps=20):
     """Bandwidth of a plain streaming copy (read + write bytes per second)."""
     from paper_1512_06025_amd import _lib
@@ -166,6 +204,8 @@ def main():
     ap.add_argument("--no-nodal", action="store_true", help="skip the dense nodal comparator")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-shot batched workload")
     ap.add_argument("--batched-steps", type=int, default=500)
+    ap.add_argument("--no-gradient", action="store_true", help="skip the misfit-gradient workload")
+    ap.add_argument("--gradient-steps", type=int, default=500)
     ap.add_argument("--no-copy-probe", action="store_true")
     ap.add_argument("--copy-probe-only", action="store_true",
                     help="only run the streaming-copy probe (counter calibration)")
@@ -257,6 +297,8 @@ def main():
         out["nodal"] = nod
     if not args.no_batched:
         out["batched"] = time_batched(P, torch, workload, args.batched_steps)
+    if not args.no_gradient:
+        out["gradient"] = time_gradient(P, torch, workload, args.gradient_steps)
     if not args.no_copy_probe:
         cp = copy_probe(torch, P)
         out["roofline"]["copy_probe_GBs"] = cp["GBs"]

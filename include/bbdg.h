@@ -235,6 +235,49 @@ int bbdg_run_batched(bbdg_solver* s, void* q, int64_t shots, const int32_t* src_
  * overwritten.  Synchronises `stream`. */
 int bbdg_tune_batched(bbdg_solver* s, int64_t shots, void* scratch, int* wpb, void* stream);
 
+/* ---- Receiver misfit and its gradient ---------------------------------------
+ * For the batched forward run above (shots, sources, receivers, t0, dt,
+ * steps) with traces d (steps x shots x R) and observations d_obs of the same
+ * shape, the misfit is J = 1/2 sum (d - d_obs)^2, and its gradient is taken
+ * with respect to m = c^2 (= kappa, rho = 1) of every element.  The
+ * gradient is the exact derivative of the discrete forward map (discrete
+ * adjoint): every stage of the scheme is reversed with the transposed
+ * operators (transposed barycentric derivatives of Lemma 1, L^{fT} =
+ * L_0 (E_L^f)^T of Section 3.1.2 evaluated by degree raising, transposed
+ * upwind flux of Section 2), and includes the dependence of the flux
+ * weights tau_p = 2/(c- + c+), tau_u = (c- + c+)/2 and of the source vector
+ * on m.  States use the solver's element type; gradient sums are FP64.
+ * The forward states are kept at checkpoints every ckpt_every steps (0 = only
+ * the initial state) and each segment is recomputed once, recording its
+ * stages, during the reverse sweep. */
+
+/* Replaces the wavespeed (host, K doubles, c > 0) of a solver; the mesh is
+ * unchanged.  Source vectors scale with kappa of their element: recompute
+ * them with bbdg_source_coeffs afterwards.  Synchronises the device. */
+int bbdg_set_wavespeed(bbdg_solver* s, const double* c);
+
+/* Bytes of device work space for bbdg_misfit / bbdg_misfit_gradient with
+ * these sizes (0 for invalid sizes). */
+size_t bbdg_misfit_work_bytes(const bbdg_solver* s, int64_t shots, int R, int64_t steps, int64_t ckpt_every);
+
+/* Runs the batched forward problem from q0 (device (shots, 4, K, Np), or NULL
+ * for zero initial states), keeps checkpoints and traces in work (device,
+ * >= bbdg_misfit_work_bytes, 256-byte aligned) and writes J (device, one
+ * double).  Arguments as bbdg_run_batched; obs: device (steps, shots, R) of
+ * the element type; R >= 1, steps >= 1. */
+int bbdg_misfit(bbdg_solver* s, int64_t shots, const void* q0, const int32_t* src_elem,
+                const void* src_coef, double f0, double ts, int R, const int32_t* rec_elem,
+                const void* rec_coef, const void* obs, double t0, double dt, int64_t steps,
+                int64_t ckpt_every, double* J, void* work, void* stream);
+
+/* Gradient dJ/dm (device, K doubles) of the misfit of the last bbdg_misfit
+ * call on the same work space, with the same arguments (its checkpoints and
+ * traces are reused). */
+int bbdg_misfit_gradient(bbdg_solver* s, int64_t shots, const void* q0, const int32_t* src_elem,
+                         const void* src_coef, double f0, double ts, int R, const int32_t* rec_elem,
+                         const void* rec_coef, const void* obs, double t0, double dt, int64_t steps,
+                         int64_t ckpt_every, double* grad, void* work, void* stream);
+
 /* Measurement aid, not part of the method: copies `bytes` (a multiple of 16,
  * both pointers 16-byte aligned, no overlap) from device buffer src to dst
  * with a plain streaming kernel on the current device.  Used to measure the
@@ -243,6 +286,10 @@ int bbdg_copy_probe(const void* src, void* dst, size_t bytes, void* stream);
 
 /* Synchronises the solver's device and frees its tables.  Accepts NULL. */
 int bbdg_destroy(bbdg_solver* s);
+
+/* The HIP error code (hipError_t) behind the last BBDG_E_LAUNCH or
+ * BBDG_E_RESIDENT returned on this thread (0 if none): a diagnostic. */
+int bbdg_last_hip_error(void);
 
 /* Static description of an error code. */
 const char* bbdg_strerror(int code);

@@ -52,6 +52,16 @@ SIGNATURES = {
                                     _c.c_int, _c.c_void_p]),
     "bbdg_tune_batched": (_c.c_int, [_c.c_void_p, _c.c_int64, _c.c_void_p, _c.POINTER(_c.c_int),
                                      _c.c_void_p]),
+    "bbdg_set_wavespeed": (_c.c_int, [_c.c_void_p, _c.c_void_p]),
+    "bbdg_misfit_work_bytes": (_c.c_size_t, [_c.c_void_p, _c.c_int64, _c.c_int, _c.c_int64, _c.c_int64]),
+    "bbdg_misfit": (_c.c_int, [_c.c_void_p, _c.c_int64, _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_double,
+                               _c.c_double, _c.c_int, _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_double,
+                               _c.c_double, _c.c_int64, _c.c_int64, _c.c_void_p, _c.c_void_p, _c.c_void_p]),
+    "bbdg_misfit_gradient": (_c.c_int, [_c.c_void_p, _c.c_int64, _c.c_void_p, _c.c_void_p, _c.c_void_p,
+                                        _c.c_double, _c.c_double, _c.c_int, _c.c_void_p, _c.c_void_p,
+                                        _c.c_void_p, _c.c_double, _c.c_double, _c.c_int64, _c.c_int64,
+                                        _c.c_void_p, _c.c_void_p, _c.c_void_p]),
+    "bbdg_last_hip_error": (_c.c_int, []),
     "bbdg_copy_probe": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_size_t, _c.c_void_p]),
     "bbdg_destroy": (_c.c_int, [_c.c_void_p]),
     "bbdg_strerror": (_c.c_char_p, [_c.c_int]),
@@ -63,7 +73,10 @@ _lib = None
 class BBDGError(RuntimeError):
     def __init__(self, code, where):
         self.code = code
-        super().__init__("%s failed: %s (%d)" % (where, ERRORS.get(code, "?"), code))
+        detail = ""
+        if code in (-8, -11) and _lib is not None:
+            detail = " [hipError %d]" % _lib.bbdg_last_hip_error()
+        super().__init__("%s failed: %s (%d)%s" % (where, ERRORS.get(code, "?"), code, detail))
 
 
 def load():

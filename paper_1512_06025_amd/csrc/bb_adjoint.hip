@@ -1,0 +1,637 @@
+// Discrete adjoint of the Bernstein-Bezier DG stage (gfx950, wave64).
+//
+// The forward stage is res <- a_s res + dt (A(m) q + f), q <- q + b_s res.
+// Its reverse, with qb and rb the adjoints of q and res, is
+//   u = rb + b_s qb,  qb <- qb + dt A^T u,  rb <- a_s u,
+//   grad_m += dt u^T d(A q + f)/dm        (q, f: the forward stage's input).
+// A^T is applied with the transposes of the kernels of the forward stage:
+//   volume: (D^{iT} x)(beta) = beta_i x(beta) + sum_{j != i} (beta_j+1) x(beta - e_i + e_j)
+//           (the transpose of the row form of Lemma 1 / Appendix A.1; the
+//           term is absent when beta_i = 0), with the chain rule transposed;
+//   surface: L^{fT} = L_0 (E_L^f)^T (Section 3.1.2; L_0 is symmetric).  The
+//           transpose of the one-degree reductions is degree raising,
+//           (E y)(b) = sum_k b_k/m y(b - e_k), so (E_L^f)^T x is evaluated by
+//           Horner's rule over the layers x_j = ell_j x|_{alpha_f = j}:
+//           y = x_N, y <- x_j + E y for j = N-1..0.  The result on the face
+//           nodes goes through the transposed upwind flux of Section 2 to the
+//           own traces and, through z_out, to the neighbours' traces, which
+//           each element pulls from z_in at the start of the next reverse
+//           stage (a face's two sides are updated by their own waves, with
+//           no atomics).
+// Gradient with respect to m_k = kappa_k = c_k^2: the pressure equation of
+// element k (with the source) is proportional to kappa_k at fixed taus, so
+// that part is u_p . P / kappa_k with P the recorded pressure right-hand
+// side; tau_p and tau_u of a face depend on s = c_k + c_+, and
+// d/ds of the face flux, contracted with the face adjoint, goes to gt and is
+// split between the two elements of the face by launch_gradient_finalize.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "bb_common.hpp"
+#include "bb_launch.hpp"
+
+namespace bbdg {
+
+namespace {
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+template <int N, typename T>
+struct AShape {
+  static constexpr int Np = np_of(N);
+  static constexpr int Nfp = nfp_of(N);
+  static constexpr int E = (Np <= 32) ? (64 / Np) : 1;
+  static constexpr int NPL = (E * Np + 63) / 64;
+  static constexpr int NFI = (E * 4 * Nfp + 63) / 64;
+  static constexpr int FB = sizeof(T) == 8 ? (N >= 8 ? 1 : (N >= 6 ? 2 : 4)) : (N >= 8 ? 2 : 4);
+  static constexpr int NV = 2 * FB;
+  static constexpr int WPB = (N >= 8) ? 2 : 4;
+  // per element geometry (T): grad lambda_0..3 (12), kappa; per face f at
+  // 16 + 8 f: g (3), a_p, a_u, b_u, |g|, d(tau terms) packed below
+  static constexpr int GEO = 48;
+};
+
+template <int N>
+struct AEll {
+  static constexpr double binom(int n, int k) {
+    double r = 1.0;
+    for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
+    return r;
+  }
+  static constexpr double value(int j) { return ((j & 1) ? -1.0 : 1.0) * binom(N, j) / (1.0 + j); }
+};
+
+}  // namespace
+
+template <int N, typename T>
+__global__ __launch_bounds__((64 * AShape<N, T>::WPB)) void bb_adjoint_kernel(AdjointArgs<T> A) {
+  using S = AShape<N, T>;
+  constexpr int Np = S::Np, Nfp = S::Nfp, E = S::E, NPL = S::NPL, NFI = S::NFI;
+  constexpr int FB = S::FB, NV = S::NV, WPB = S::WPB, GEO = S::GEO;
+  constexpr TabLayout L = tab_layout(N);
+
+  __shared__ uint16_t t_fnode[4 * Nfp];
+  __shared__ uint16_t t_fperm[6 * Nfp];
+  __shared__ uint32_t t_alpha[Np];
+  __shared__ uint16_t t_vnbr[Np][12];
+  __shared__ uint16_t t_proj[Np][4];
+  __shared__ T t_ell[N + 1];
+  __shared__ uint8_t t_l0p[Nfp][8];
+  __shared__ T t_l0c[7][Nfp];
+  // degree raising into layer position nn (layers of the face-3 view):
+  // sources in the next layer and weights b_k / m
+  __shared__ uint16_t t_rsp[Np][3];
+  __shared__ T t_rsc[3][Np];
+
+  __shared__ T su[WPB][E][4][Np];       // u = rb + b_s qb
+  __shared__ T sh[WPB][E][4][Np];       // h_i = grad(lambda_i) . u_vel
+  __shared__ T slev[WPB][E][NV][Np];    // layered face vectors
+  __shared__ T sfl[WPB][E][NV][Nfp];    // L^{fT} results on the face nodes
+  __shared__ T sface[WPB][E][4][2][Nfp];  // per-face node contributions
+  __shared__ double sred[WPB][E][5];    // gradient partial sums
+  __shared__ T sgeo[WPB][E][GEO];
+  __shared__ int32_t she[WPB][E * 4];
+  __shared__ uint8_t shf[WPB][E * 4];
+
+  const int tid = threadIdx.x;
+  for (int i = tid; i < 4 * Nfp; i += 64 * WPB) t_fnode[i] = A.tab[L.fnode + i];
+  for (int i = tid; i < 6 * Nfp; i += 64 * WPB) t_fperm[i] = A.tab[L.fperm + i];
+  for (int i = tid; i < Np; i += 64 * WPB) {
+    const uint16_t* a = A.tab + L.alpha + 4 * i;
+    t_alpha[i] = (uint32_t)a[0] | ((uint32_t)a[1] << 8) | ((uint32_t)a[2] << 16) | ((uint32_t)a[3] << 24);
+    for (int p = 0; p < 12; ++p) t_vnbr[i][p] = A.tab[L.vnbr + 12 * i + p];
+    for (int f = 0; f < 4; ++f) t_proj[i][f] = A.tab[L.proj + 4 * i + f];
+  }
+  if (tid <= N) {
+    double e = 0.0;
+    for (int j = 0; j <= N; ++j) e = (tid == j) ? AEll<N>::value(j) : e;
+    t_ell[tid] = (T)e;
+  }
+  __syncthreads();
+  for (int gg = tid; gg < Nfp; gg += 64 * WPB) {
+    const uint32_t ap = t_alpha[gg];
+    const int b0 = ap & 255, b1 = (ap >> 8) & 255, b2 = (ap >> 16) & 255;
+    const int row = tri_row(b2, N);
+    const int rdn = b2 >= 1 ? tri_row(b2 - 1, N) : 0;
+    const int rup = tri_row(b2 + 1, N);
+    const int pos[6] = {row + b1 - 1, rup + b1 - 1, rdn + b1, rdn + b1 + 1, row + b1 + 1, rup + b1};
+    const int cw[6] = {(b0 + 1) * b1, (b2 + 1) * b1, (b0 + 1) * b2, (b1 + 1) * b2, (b1 + 1) * b0, (b2 + 1) * b0};
+    t_l0p[gg][0] = (uint8_t)gg;
+    t_l0c[0][gg] = (T)(0.5 * ((b0 + 1) * (b0 + 1) + (b1 + 1) * (b1 + 1) + (b2 + 1) * (b2 + 1)));
+    for (int q = 0; q < 6; ++q) {
+      t_l0p[gg][1 + q] = (uint8_t)(cw[q] ? pos[q] : gg);
+      t_l0c[1 + q][gg] = (T)(0.5 * cw[q]);
+    }
+    t_l0p[gg][7] = (uint8_t)gg;
+  }
+  for (int nn = tid; nn < Np; nn += 64 * WPB) {
+    // position nn = layer j = alpha_3 of volume node nn, face-local (b0,b1,b2),
+    // |b| = m = N - j; sources b - e_k in layer j + 1 (degree m - 1)
+    const uint32_t ap = t_alpha[nn];
+    const int b0 = ap & 255, b1 = (ap >> 8) & 255, b2 = (ap >> 16) & 255, j = ap >> 24;
+    const int m = N - j;
+    if (m == 0) {
+      for (int k = 0; k < 3; ++k) {
+        t_rsp[nn][k] = (uint16_t)nn;
+        t_rsc[k][nn] = (T)0;
+      }
+      continue;
+    }
+    const int in0 = level_off(j + 1, N);
+    t_rsp[nn][0] = (uint16_t)(b0 >= 1 ? in0 + tri_row(b2, m - 1) + b1 : nn);
+    t_rsp[nn][1] = (uint16_t)(b1 >= 1 ? in0 + tri_row(b2, m - 1) + b1 - 1 : nn);
+    t_rsp[nn][2] = (uint16_t)(b2 >= 1 ? in0 + tri_row(b2 - 1, m - 1) + b1 : nn);
+    t_rsc[0][nn] = (T)((double)b0 / m);
+    t_rsc[1][nn] = (T)((double)b1 / m);
+    t_rsc[2][nn] = (T)((double)b2 / m);
+  }
+  __syncthreads();
+
+  const int lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int64_t K = A.K;
+  const int64_t KNp = K * Np;
+  const int64_t G = (K + E - 1) / E;
+  const int64_t GS = G * A.shots;
+  const int xcd = blockIdx.x & 7;
+  const int64_t g_lo = GS * xcd / 8, g_hi = GS * (xcd + 1) / 8;
+  const int64_t wstride = (int64_t)(gridDim.x >> 3) * WPB;
+  const T a_s = A.a_s, b_s = A.b_s, dt = A.dt;
+
+  for (int64_t g = g_lo + (int64_t)(blockIdx.x >> 3) * WPB + w; g < g_hi; g += wstride) {
+    const int64_t shot = (int64_t)((uint32_t)g / (uint32_t)G);
+    const int64_t e0 = (g - shot * G) * E;
+    const int64_t sb = shot * 4 * KNp;
+    const int64_t zb = shot * K * 8 * Nfp;
+
+    // ---- geometry and connectivity ----------------------------------------------
+    wave_sync();
+    for (int v = lane; v < E * 4; v += 64) {
+      const int el = v >> 2, f = v & 3;
+      const int64_t k = e0 + el;
+      T* o = sgeo[w][el];
+      if (k >= K) {  // ragged tail: neutral geometry, no neighbours
+        for (int c = 0; c < 3; ++c) o[3 * f + c] = 0;
+        if (f == 0) o[12] = 1;
+        for (int c = 0; c < 8; ++c) o[16 + 8 * f + c] = 1;
+        she[w][v] = -1;
+        shf[w][v] = 0;
+        continue;
+      }
+      const double* ge = A.geo + k * kGeoStride;
+      double gx, gy, gz;
+      if (f == 0) {
+        gx = -(ge[0] + ge[3] + ge[6]);
+        gy = -(ge[1] + ge[4] + ge[7]);
+        gz = -(ge[2] + ge[5] + ge[8]);
+      } else {
+        gx = ge[3 * (f - 1) + 0];
+        gy = ge[3 * (f - 1) + 1];
+        gz = ge[3 * (f - 1) + 2];
+      }
+      o[3 * f + 0] = (T)gx;
+      o[3 * f + 1] = (T)gy;
+      o[3 * f + 2] = (T)gz;
+      if (f == 0) o[12] = (T)ge[9];
+      const double F = 2.0 * sqrt(gx * gx + gy * gy + gz * gz);
+      T* fr = o + 16 + 8 * f;
+      fr[0] = (T)(-2.0 * gx);
+      fr[1] = (T)(-2.0 * gy);
+      fr[2] = (T)(-2.0 * gz);
+      fr[3] = (T)ge[10 + f];     // a_p = kappa |g| / s
+      fr[4] = (T)(0.5 * ge[9]);  // a_u = kappa / 2
+      fr[5] = (T)ge[14 + f];     // b_u = s / (4 |g|)
+      fr[6] = (T)F;
+      fr[7] = (T)0;
+      she[w][v] = A.etoe[k * 4 + f];
+      shf[w][v] = A.etofo[k * 4 + f];
+    }
+    wave_sync();
+
+    // ---- own values --------------------------------------------------------------
+    T qv[NPL][4], uv[NPL][4], pv[NPL];
+    uint32_t noff[NPL];
+#pragma unroll
+    for (int r = 0; r < NPL; ++r) {
+      const int v = lane + 64 * r;
+      const int el = v / Np;
+      const int n = v - el * Np;
+      const bool ok = (v < E * Np) && (e0 + el < K);
+      noff[r] = ok ? (uint32_t)((e0 + el) * Np + n) : 0u;
+#pragma unroll
+      for (int f = 0; f < 4; ++f) {
+        qv[r][f] = ok ? A.qb[sb + f * KNp + noff[r]] : (T)0;
+        uv[r][f] = ok ? A.rb[sb + f * KNp + noff[r]] : (T)0;
+      }
+      pv[r] = ok ? A.rec_p[shot * KNp + noff[r]] : (T)0;
+    }
+
+    // ---- neighbour terms of the previous reverse stage -----------------------------
+    if (A.pull) {
+#pragma unroll
+      for (int r = 0; r < NFI; ++r) {
+        const int v = lane + 64 * r;
+        if (v >= E * 4 * Nfp) continue;
+        const int el = v / (4 * Nfp);
+        const int rem = v - el * 4 * Nfp;
+        const int f = rem / Nfp;
+        const int gg = rem - f * Nfp;
+        T zp = 0, zu = 0;
+        const int nb = she[w][el * 4 + f];
+        if (nb >= 0) {
+          const int info = shf[w][el * 4 + f];
+          const int g2 = t_fperm[(info >> 2) * Nfp + gg];
+          const T* zs = A.z_in + zb + ((int64_t)nb * 4 + (info & 3)) * 2 * Nfp + g2;
+          zp = zs[0];
+          zu = zs[Nfp];
+        }
+        // the neighbour's g is -(|g_nb|/|g_f|) g_f and zu carries |g_nb|:
+        // the velocity adjoint gains -(g_f/|g_f|) zu
+        sface[w][el][f][0][gg] = zp;
+        sface[w][el][f][1][gg] = -zu / sgeo[w][el][16 + 8 * f + 6];
+      }
+      wave_sync();
+#pragma unroll
+      for (int r = 0; r < NPL; ++r) {
+        const int v = lane + 64 * r;
+        if (v >= E * Np) continue;
+        const int el = v / Np;
+        const int n = v - el * Np;
+        const uint32_t ap = t_alpha[n];
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+          if ((ap >> (8 * f)) & 255) continue;
+          const int gg = t_proj[n][f];
+          const T* fr = sgeo[w][el] + 16 + 8 * f;
+          const T cp = sface[w][el][f][0][gg], cu = sface[w][el][f][1][gg];
+          qv[r][0] += dt * cp;
+          qv[r][1] += dt * fr[0] * cu;
+          qv[r][2] += dt * fr[1] * cu;
+          qv[r][3] += dt * fr[2] * cu;
+        }
+      }
+    }
+
+    // ---- u = rb + b_s qb; h_i = grad(lambda_i) . u_vel ------------------------------
+    T kpart[NPL];
+#pragma unroll
+    for (int r = 0; r < NPL; ++r) {
+      const int v = lane + 64 * r;
+      kpart[r] = 0;
+      if (v >= E * Np) continue;
+      const int el = v / Np;
+      const int n = v - el * Np;
+#pragma unroll
+      for (int f = 0; f < 4; ++f) {
+        uv[r][f] += b_s * qv[r][f];
+        su[w][el][f][n] = uv[r][f];
+      }
+      const T* ge = sgeo[w][el];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) sh[w][el][i][n] = ge[3 * i] * uv[r][1] + ge[3 * i + 1] * uv[r][2] + ge[3 * i + 2] * uv[r][3];
+      kpart[r] = uv[r][0] * pv[r];
+    }
+    wave_sync();
+
+    // ---- volume: transposed derivatives ---------------------------------------------
+    T acc[NPL][4];
+#pragma unroll
+    for (int r = 0; r < NPL; ++r) {
+#pragma unroll
+      for (int f = 0; f < 4; ++f) acc[r][f] = 0;
+      const int v = lane + 64 * r;
+      if (v >= E * Np) continue;
+      const int el = v / Np;
+      const int n = v - el * Np;
+      const uint32_t ap = t_alpha[n];
+      const int bi[4] = {(int)(ap & 255), (int)((ap >> 8) & 255), (int)((ap >> 16) & 255), (int)(ap >> 24)};
+      const T* ge = sgeo[w][el];
+      T tp[4], ph = 0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        // (D^{iT} x)(beta) for x = u_p and x = h_i
+        T a = (T)bi[i] * su[w][el][0][n];
+        T b = (T)bi[i] * sh[w][el][i][n];
+        if (bi[i] >= 1) {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            if (j == i) continue;
+            const int src = t_vnbr[n][3 * j + (i < j ? i : i - 1)];  // beta + e_j - e_i
+            const T c = (T)(bi[j] + 1);
+            a += c * su[w][el][0][src];
+            b += c * sh[w][el][i][src];
+          }
+        }
+        tp[i] = a;
+        ph += b;
+      }
+      acc[r][0] = -ph;
+#pragma unroll
+      for (int d = 0; d < 3; ++d)
+        acc[r][1 + d] = -ge[12] * (ge[d] * tp[0] + ge[3 + d] * tp[1] + ge[6 + d] * tp[2] + ge[9 + d] * tp[3]);
+    }
+
+    // ---- surface: L^{fT} on the face vectors, FB faces at a time ---------------------
+    for (int fb0 = 0; fb0 < 4; fb0 += FB) {
+      // layers: x_j(position) = ell_j x(alpha) over alpha with alpha_f = j
+#pragma unroll
+      for (int r = 0; r < NPL; ++r) {
+        const int v = lane + 64 * r;
+        if (v >= E * Np) continue;
+        const int el = v / Np;
+        const int n = v - el * Np;
+        const uint32_t ap = t_alpha[n];
+#pragma unroll
+        for (int fl = 0; fl < FB; ++fl) {
+          const int f = fb0 + fl;
+          const T* fr = sgeo[w][el] + 16 + 8 * f;
+          const T ell = t_ell[(ap >> (8 * f)) & 255];
+          const int pos = t_proj[n][f];
+          slev[w][el][fl][pos] = ell * uv[r][0];
+          slev[w][el][FB + fl][pos] = ell * (fr[0] * uv[r][1] + fr[1] * uv[r][2] + fr[2] * uv[r][3]);
+        }
+      }
+      wave_sync();
+      // Horner over the layers: y_j = x_j + E y_{j+1}, j = N-1 .. 0
+      for (int j = N - 1; j >= 0; --j) {
+        const int out0 = level_off(j, N);
+        const int Tm = tri_of(N - j);
+        for (int v = lane; v < E * NV * Tm; v += 64) {
+          const int s = v % Tm;
+          const int rest = v / Tm;
+          const int vec = rest % NV;
+          const int el = rest / NV;
+          const int nn = out0 + s;
+          T* wv = slev[w][el][vec];
+          wv[nn] += t_rsc[0][nn] * wv[t_rsp[nn][0]] + t_rsc[1][nn] * wv[t_rsp[nn][1]] +
+                    t_rsc[2][nn] * wv[t_rsp[nn][2]];
+        }
+        wave_sync();
+      }
+      // z = L_0 y_0 (L_0 symmetric)
+      for (int v = lane; v < E * NV * Nfp; v += 64) {
+        const int gg = v % Nfp;
+        const int rest = v / Nfp;
+        const int vec = rest % NV;
+        const int el = rest / NV;
+        const T* sv = slev[w][el][vec];
+        T z = 0;
+#pragma unroll
+        for (int q = 0; q < 7; ++q) z += t_l0c[q][gg] * sv[t_l0p[gg][q]];
+        sfl[w][el][vec][gg] = z;
+      }
+      wave_sync();
+      // transposed flux on the face nodes of this batch
+#pragma unroll
+      for (int r = 0; r < NFI; ++r) {
+        const int v = lane + 64 * r;
+        if (v >= E * 4 * Nfp) continue;
+        const int el = v / (4 * Nfp);
+        const int rem = v - el * 4 * Nfp;
+        const int f = rem / Nfp;
+        const int gg = rem - f * Nfp;
+        if (f < fb0 || f >= fb0 + FB) continue;
+        const int64_t k = e0 + el;
+        T dp = 0, du = 0, tau = 0;
+        if (k < K) {
+          const T* fr = sgeo[w][el] + 16 + 8 * f;
+          const T zp = sfl[w][el][f - fb0][gg], zu = sfl[w][el][FB + f - fb0][gg];
+          // sp = a_p [[p]] - a_u g.[[u]],  su = b_u g.[[u]] - [[p]]/2
+          const T jbp = fr[3] * zp - (T)0.5 * zu;
+          const T jbg = fr[5] * zu - fr[4] * zp;
+          T* zo = A.z_out + zb + (k * 4 + f) * 2 * Nfp + gg;
+          zo[0] = jbp;
+          zo[Nfp] = fr[6] * jbg;
+          const int nb = she[w][el * 4 + f];
+          if (nb >= 0) {
+            dp = -jbp;
+            du = -jbg;
+          } else if (A.bc == 0) {
+            du = (T)(-2) * jbg;
+          } else {
+            dp = (T)(-2) * jbp;
+          }
+          // d/ds of the flux at fixed jumps: -a_p/s [[p]] and g.[[u]]/(4|g|), s = 4 |g| b_u
+          const T* rj = A.rec_j + (shot * K + k) * 8 * Nfp + f * 2 * Nfp + gg;
+          const T s = (T)4 * fr[6] * fr[5];
+          tau = zp * (-fr[3] / s) * rj[0] + zu * rj[Nfp] / ((T)4 * fr[6]);
+        }
+        sface[w][el][f][0][gg] = dp;
+        sface[w][el][f][1][gg] = du;
+        sfl[w][el][f - fb0][gg] = tau;  // z no longer needed: reuse for the tau term
+      }
+      wave_sync();
+      for (int v = lane; v < E * FB; v += 64) {
+        const int el = v / FB, fl = v - el * FB;
+        double t = 0.0;
+        for (int gg = 0; gg < Nfp; ++gg) t += (double)sfl[w][el][fl][gg];
+        sred[w][el][1 + fb0 + fl] = t;
+      }
+      wave_sync();
+    }
+
+    // ---- own face contributions ---------------------------------------------------
+#pragma unroll
+    for (int r = 0; r < NPL; ++r) {
+      const int v = lane + 64 * r;
+      if (v >= E * Np) continue;
+      const int el = v / Np;
+      const int n = v - el * Np;
+      const uint32_t ap = t_alpha[n];
+#pragma unroll
+      for (int f = 0; f < 4; ++f) {
+        if ((ap >> (8 * f)) & 255) continue;
+        const int gg = t_proj[n][f];
+        const T* fr = sgeo[w][el] + 16 + 8 * f;
+        const T cp = sface[w][el][f][0][gg], cu = sface[w][el][f][1][gg];
+        acc[r][0] += cp;
+        acc[r][1] += fr[0] * cu;
+        acc[r][2] += fr[1] * cu;
+        acc[r][3] += fr[2] * cu;
+      }
+    }
+
+    // ---- kappa part of the gradient: sum_n u_p P / kappa ------------------------------
+#pragma unroll
+    for (int r = 0; r < NPL; ++r) {
+      const int v = lane + 64 * r;
+      if (v >= E * Np) continue;
+      const int el = v / Np;
+      const int n = v - el * Np;
+      su[w][el][0][n] = kpart[r];
+    }
+    wave_sync();
+    for (int el = lane; el < E; el += 64) {
+      double t = 0.0;
+      for (int n = 0; n < Np; ++n) t += (double)su[w][el][0][n];
+      sred[w][el][0] = t;
+    }
+    wave_sync();
+    for (int v = lane; v < E * 5; v += 64) {
+      const int el = v / 5, c = v - el * 5;
+      const int64_t k = e0 + el;
+      if (k >= K) continue;
+      if (c == 0) {
+        A.gk[shot * K + k] += (double)dt * sred[w][el][0] / (double)sgeo[w][el][12];
+      } else {
+        A.gt[(shot * K + k) * 4 + c - 1] += (double)dt * sred[w][el][c];
+      }
+    }
+
+    // ---- update ------------------------------------------------------------------------
+#pragma unroll
+    for (int r = 0; r < NPL; ++r) {
+      const int v = lane + 64 * r;
+      const int el = v / Np;
+      if (v >= E * Np || e0 + el >= K) continue;
+#pragma unroll
+      for (int f = 0; f < 4; ++f) {
+        A.qb[sb + f * KNp + noff[r]] = qv[r][f] + dt * acc[r][f];
+        A.rb[sb + f * KNp + noff[r]] = a_s * uv[r][f];
+      }
+    }
+  }
+}
+
+template <int N, typename T>
+static hipError_t launch_adjoint_one(const AdjointArgs<T>& a, hipStream_t stream) {
+  using S = AShape<N, T>;
+  const int64_t groups = (a.K + S::E - 1) / S::E * a.shots;
+  if (groups <= 0) return hipSuccess;
+  static int resident = 0, cus = 0;
+  if (resident == 0) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return hipErrorInvalidDevice;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      return hipErrorInvalidDevice;
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, bb_adjoint_kernel<N, T>, 64 * S::WPB, 0) != hipSuccess)
+      return hipErrorInvalidValue;
+    resident = occ > 0 ? occ : 1;
+  }
+  const int64_t needed = (groups + S::WPB - 1) / S::WPB;
+  int64_t grid = (int64_t)resident * cus;
+  if (grid > needed) grid = needed;
+  grid = ((grid + 7) / 8) * 8;
+  (void)hipGetLastError();  // drop errors left by earlier, unrelated calls
+  hipLaunchKernelGGL((bb_adjoint_kernel<N, T>), dim3((unsigned)grid), dim3(64 * S::WPB), 0, stream, a);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_adjoint_stage(int N, const AdjointArgs<T>& a, hipStream_t stream) {
+  switch (N) {
+    case 1: return launch_adjoint_one<1, T>(a, stream);
+    case 2: return launch_adjoint_one<2, T>(a, stream);
+    case 3: return launch_adjoint_one<3, T>(a, stream);
+    case 4: return launch_adjoint_one<4, T>(a, stream);
+    case 5: return launch_adjoint_one<5, T>(a, stream);
+    case 6: return launch_adjoint_one<6, T>(a, stream);
+    case 7: return launch_adjoint_one<7, T>(a, stream);
+    case 8: return launch_adjoint_one<8, T>(a, stream);
+    case 9: return launch_adjoint_one<9, T>(a, stream);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template hipError_t launch_adjoint_stage<double>(int, const AdjointArgs<double>&, hipStream_t);
+template hipError_t launch_adjoint_stage<float>(int, const AdjointArgs<float>&, hipStream_t);
+
+// ---- small kernels around the reverse sweep ---------------------------------------------
+
+template <typename T>
+__global__ void inject_receivers_kernel(int Np, int64_t K, int64_t shots, int R, const int32_t* rec_elem,
+                                        const T* rec_coef, const T* traces, const T* obs, T* qb) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= shots * Np) return;
+  const int64_t s = t / Np;
+  const int n = (int)(t - s * Np);
+  T* qp = qb + s * 4 * K * Np;  // pressure field of shot s
+  for (int r = 0; r < R; ++r) {
+    const int32_t e = rec_elem[r];
+    if (e < 0 || e >= K) continue;
+    const T res = traces[s * R + r] - obs[s * R + r];
+    qp[(int64_t)e * Np + n] += res * rec_coef[(int64_t)r * Np + n];
+  }
+}
+
+template <typename T>
+hipError_t launch_inject_receivers(int Np, int64_t K, int64_t shots, int R, const int32_t* rec_elem,
+                                   const T* rec_coef, const T* traces, const T* obs, T* qb, hipStream_t stream) {
+  const int64_t n = shots * Np;
+  if (n <= 0 || R <= 0) return hipSuccess;
+  (void)hipGetLastError();  // drop errors left by earlier, unrelated calls
+  hipLaunchKernelGGL(inject_receivers_kernel<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, Np, K,
+                     shots, R, rec_elem, rec_coef, traces, obs, qb);
+  return hipGetLastError();
+}
+
+template hipError_t launch_inject_receivers<double>(int, int64_t, int64_t, int, const int32_t*, const double*,
+                                                    const double*, const double*, double*, hipStream_t);
+template hipError_t launch_inject_receivers<float>(int, int64_t, int64_t, int, const int32_t*, const float*,
+                                                   const float*, const float*, float*, hipStream_t);
+
+template <typename T>
+__global__ __launch_bounds__(256) void misfit_kernel(int64_t n, const T* traces, const T* obs, double* J) {
+  __shared__ double part[256];
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) {
+    const double d = (double)traces[i] - (double)obs[i];
+    s += d * d;
+  }
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) J[0] = 0.5 * part[0];
+}
+
+template <typename T>
+hipError_t launch_misfit(int64_t n, const T* traces, const T* obs, double* J, hipStream_t stream) {
+  (void)hipGetLastError();  // drop errors left by earlier, unrelated calls
+  hipLaunchKernelGGL(misfit_kernel<T>, dim3(1), dim3(256), 0, stream, n, traces, obs, J);
+  return hipGetLastError();
+}
+
+template hipError_t launch_misfit<double>(int64_t, const double*, const double*, double*, hipStream_t);
+template hipError_t launch_misfit<float>(int64_t, const float*, const float*, double*, hipStream_t);
+
+__global__ void gradient_finalize_kernel(int64_t K, int64_t shots, const double* geo, const int32_t* etoe,
+                                         const uint8_t* etofo, const double* gk, const double* gt, double* grad) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= K) return;
+  const double c = sqrt(geo[k * kGeoStride + 9]);
+  double total = 0.0;
+  for (int64_t s = 0; s < shots; ++s) {
+    double tau = 0.0;
+    for (int f = 0; f < 4; ++f) {
+      const int32_t nb = etoe[k * 4 + f];
+      const double own = gt[(s * K + k) * 4 + f];
+      if (nb < 0) {
+        tau += 2.0 * own;
+      } else {
+        tau += own + gt[(s * K + nb) * 4 + (etofo[k * 4 + f] & 3)];
+      }
+    }
+    total += gk[s * K + k] + tau / (2.0 * c);
+  }
+  grad[k] = total;
+}
+
+hipError_t launch_gradient_finalize(int64_t K, int64_t shots, const double* geo, const int32_t* etoe,
+                                    const uint8_t* etofo, const double* gk, const double* gt, double* grad,
+                                    hipStream_t stream) {
+  if (K <= 0) return hipSuccess;
+  (void)hipGetLastError();  // drop errors left by earlier, unrelated calls
+  hipLaunchKernelGGL(gradient_finalize_kernel, dim3((unsigned)((K + 255) / 256)), dim3(256), 0, stream, K, shots,
+                     geo, etoe, etofo, gk, gt, grad);
+  return hipGetLastError();
+}
+
+}  // namespace bbdg

@@ -44,7 +44,7 @@ constexpr int64_t kMaxFieldElems = (int64_t)1 << 31;
 //   proj    [Np][4]      position of node alpha in the face-layered vector of
 //                        face f: level_off(alpha_f) + tri_row(alpha_v2) + alpha_v1
 struct TabLayout {
-  int Np, Nfp, alpha, vnbr, fnode, nbrnode, proj, size;
+  int Np, Nfp, alpha, vnbr, fnode, nbrnode, proj, fperm, size;
 };
 
 constexpr TabLayout tab_layout(int N) {
@@ -56,7 +56,8 @@ constexpr TabLayout tab_layout(int N) {
   t.fnode = t.vnbr + 12 * t.Np;
   t.nbrnode = t.fnode + 4 * t.Nfp;
   t.proj = t.nbrnode + 24 * t.Nfp;
-  t.size = t.proj + 4 * t.Np;
+  t.fperm = t.proj + 4 * t.Np;
+  t.size = t.fperm + 6 * t.Nfp;
   return t;
 }
 

@@ -36,6 +36,11 @@ struct StageArgs {
   const int32_t* rec_elem;  // R
   const T* rec_coef;        // R x Np: B_alpha(lambda_r)
   T* traces;                // steps x S x R
+  // Optional record of every stage for the adjoint (batched mode): the
+  // pressure right-hand side incl. source, (stages, S, K, Np), and the jumps
+  // [[p]], g_f.[[u]] on the own face nodes, (stages, S, K, 4, 2, Nfp).
+  T* rec_p;
+  T* rec_j;
 };
 
 template <typename T>
@@ -50,6 +55,50 @@ hipError_t launch_batched(int N, int wpb, const StageArgs<T>& a, hipStream_t str
 // geometry and connectivity plus the dense operators
 //   dr   [3][NpP][Kv]  Dr_i = V (D^i - D^0) V^{-1}, zero padded
 //   lift [NpP][Kl]     the four face lifts side by side, zero padded
+// One reverse stage of the discrete adjoint of the batched LSRK4 run.
+//   u = rb + b_s qb (qb completed with the neighbour terms of the previous
+//   reverse stage, z_in), qb <- qb + dt A^T u (own-element part), rb <- a_s u,
+//   z_out = the face adjoint each neighbour needs, and the gradient terms
+//   of this stage are added to gk (S, K) and gt (S, K, 4) in FP64.
+template <typename T>
+struct AdjointArgs {
+  T* rb;             // (S, 4, K, Np) in/out
+  T* qb;             // (S, 4, K, Np) in/out, own-element part
+  const T* z_in;     // (S, K, 4, 2, Nfp) of the previous reverse stage (pull != 0)
+  T* z_out;          // (S, K, 4, 2, Nfp)
+  const T* rec_p;    // (S, K, Np) record of this forward stage
+  const T* rec_j;    // (S, K, 4, 2, Nfp)
+  double* gk;        // (S, K)
+  double* gt;        // (S, K, 4)
+  const double* geo;
+  const int32_t* etoe;
+  const uint8_t* etofo;
+  const uint16_t* tab;
+  int64_t K, shots;
+  T a_s, b_s, dt;
+  int pull;
+  int bc;
+};
+
+template <typename T>
+hipError_t launch_adjoint_stage(int N, const AdjointArgs<T>& a, hipStream_t stream);
+
+// qb[s][0][rec_elem[r]] += (traces[s][r] - obs[s][r]) rec_coef[r] for one step
+// (traces, obs: (S, R) slices), receivers in order (deterministic).
+template <typename T>
+hipError_t launch_inject_receivers(int Np, int64_t K, int64_t shots, int R, const int32_t* rec_elem,
+                                   const T* rec_coef, const T* traces, const T* obs, T* qb, hipStream_t stream);
+
+// J = 1/2 sum (traces - obs)^2 over n values, accumulated in FP64 by one workgroup.
+template <typename T>
+hipError_t launch_misfit(int64_t n, const T* traces, const T* obs, double* J, hipStream_t stream);
+
+// grad[k] = sum_s gk[s][k] + (1/(2 c_k)) (sum_f w_f gt[s][k][f] + sum_f gt[s][nb][nf]),
+// w_f = 2 on boundary faces (c+ = c there) else 1, second sum over interior faces.
+hipError_t launch_gradient_finalize(int64_t K, int64_t shots, const double* geo, const int32_t* etoe,
+                                    const uint8_t* etofo, const double* gk, const double* gt, double* grad,
+                                    hipStream_t stream);
+
 template <typename T>
 struct NodalArgs {
   const T* qin;

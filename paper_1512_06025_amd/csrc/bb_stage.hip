@@ -468,6 +468,11 @@ void bb_stage_kernel(StageArgs<T> A) {
             }
             sp = fr[3] * jp - fr[4] * jgu;
             su = fr[5] * jgu - (T)0.5 * jp;
+            if (kBatch && A.rec_j) {
+              T* rj = A.rec_j + ((stage * A.shots + shot) * K + e0 + el) * (8 * Nfp) + f * (2 * Nfp) + gg;
+              rj[0] = jp;
+              rj[Nfp] = jgu;
+            }
           }
           sfl[w][el][f - fb0][gg] = sp;
           sfl[w][el][FB + f - fb0][gg] = su;
@@ -558,6 +563,7 @@ void bb_stage_kernel(StageArgs<T> A) {
       if (v >= E * Np || e0 + el >= K) continue;
       const uint32_t off = noff[r];
       if constexpr (kUpdate) {
+        if (kBatch && A.rec_p) A.rec_p[(stage * A.shots + shot) * KNp + off] = rhs[r][0];
         const T dt = kBatch ? (T)A.dtd : A.dt;
 #pragma unroll
         for (int f = 0; f < 4; ++f) {
@@ -629,6 +635,7 @@ static hipError_t launch_one(const StageArgs<T>& a, hipStream_t stream) {
   int64_t grid = 0;
   const hipError_t e = resident_grid<N, T, MODE, 4>(groups, &grid);
   if (e != hipSuccess) return e;
+  (void)hipGetLastError();  // drop errors left by earlier, unrelated calls
   hipLaunchKernelGGL((bb_stage_kernel<N, T, MODE, 4>), dim3((unsigned)grid), dim3(256), 0, stream, a);
   return hipGetLastError();
 }

@@ -27,6 +27,8 @@ struct bbdg_solver {
   uint8_t* d_etofo = nullptr;  // K x 4
   uint16_t* d_tab = nullptr;   // tab_layout(N).size
   std::vector<double> h_J, h_kappa;  // host copies for the source vectors
+  std::vector<double> h_geo;         // K x 10 as passed to create
+  std::vector<int32_t> h_etoe;       // K x 4
   int64_t tuned_shots = 0;           // shot count bbdg_tune_batched ran for
   int tuned_wpb = 0;                 // and the waves per workgroup it chose
 };
@@ -104,6 +106,7 @@ std::vector<uint16_t> build_tables(int N) {
         for (int m = 0; m < 3; ++m) gp[kPerm[o][m]] = T[g][m];
         const int local = tri_row(gp[2], N) + gp[1];
         t[L.nbrnode + (f2 * 6 + o) * L.Nfp + g] = t[L.fnode + f2 * L.Nfp + local];
+        if (f2 == 0) t[L.fperm + o * L.Nfp + g] = (uint16_t)local;
       }
   return t;
 }
@@ -123,6 +126,14 @@ int perm_inverse(int o) {
 }
 
 size_t elem_size(int dtype) { return dtype == BBDG_F64 ? sizeof(double) : sizeof(float); }
+
+// HIP error behind the last BBDG_E_LAUNCH / BBDG_E_DEVICE of this thread.
+thread_local int g_last_hip_error = 0;
+
+int hip_fail(hipError_t e, int code) {
+  g_last_hip_error = (int)e;
+  return code;
+}
 
 template <typename T>
 StageArgs<T> base_args(const bbdg_solver* s) {
@@ -172,8 +183,8 @@ int run_typed(bbdg_solver* s, T* q, T* work, double dt, int64_t steps, hipStream
   T* nxt = work + n;
   for (int64_t it = 0; it < steps; ++it) {
     for (int st5 = 0; st5 < 5; ++st5) {
-      if (launch_any<T>(s, kStage, cur, nxt, res, (T)kRkA[st5], (T)kRkB[st5], (T)dt, st5 != 0, st) != hipSuccess)
-        return BBDG_E_LAUNCH;
+      const hipError_t le = launch_any<T>(s, kStage, cur, nxt, res, (T)kRkA[st5], (T)kRkB[st5], (T)dt, st5 != 0, st);
+      if (le != hipSuccess) return hip_fail(le, BBDG_E_LAUNCH);
       std::swap(cur, nxt);
     }
   }
@@ -472,8 +483,8 @@ int run_batched_typed(bbdg_solver* s, T* q, int64_t shots, const int32_t* src_el
   a.rec_coef = rec_coef;
   a.traces = traces;
   const hipError_t e = launch_batched<T>(s->N, wpb, a, st);
-  if (e == hipErrorCooperativeLaunchTooLarge || e == hipErrorInvalidConfiguration) return BBDG_E_RESIDENT;
-  if (e != hipSuccess) return BBDG_E_LAUNCH;
+  if (e == hipErrorCooperativeLaunchTooLarge || e == hipErrorInvalidConfiguration) return hip_fail(e, BBDG_E_RESIDENT);
+  if (e != hipSuccess) return hip_fail(e, BBDG_E_LAUNCH);
   // an odd stage count leaves the state in the second buffer
   if ((a.nstages & 1) &&
       hipMemcpyAsync(q, a.qalt, (size_t)(shots * n) * sizeof(T), hipMemcpyDeviceToDevice, st) != hipSuccess)
@@ -487,6 +498,150 @@ bool batched_shape_ok(const bbdg_solver* s, int64_t shots) {
   const int64_t E = Np <= 32 ? 64 / Np : 1;
   const int64_t G = (s->K + E - 1) / E;
   return shots <= ((int64_t)1 << 32) / G - 1;
+}
+
+// Work-space layout of the misfit and its gradient (offsets in bytes, each
+// part 256-byte aligned).
+struct GradLayout {
+  int64_t C = 0, nseg = 0;
+  size_t state = 0, fwork = 0, ckpt = 0, traces = 0, rec_p = 0, rec_j = 0, rb = 0, qb = 0, z = 0, gk = 0, gt = 0;
+  size_t total = 0;
+};
+
+GradLayout grad_layout(const bbdg_solver* s, int64_t shots, int R, int64_t steps, int64_t ckpt_every) {
+  GradLayout g;
+  g.C = (ckpt_every <= 0 || ckpt_every > steps) ? steps : ckpt_every;
+  g.nseg = g.C > 0 ? (steps + g.C - 1) / g.C : 0;
+  const size_t w = elem_size(s->dtype);
+  const size_t Np = (size_t)np_of(s->N), Nfp = (size_t)nfp_of(s->N), K = (size_t)s->K, S = (size_t)shots;
+  const size_t st = S * 4 * K * Np * w;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off += (bytes + 255) / 256 * 256;
+    return at;
+  };
+  g.state = take(st);
+  g.fwork = take(2 * st);
+  g.ckpt = take((size_t)g.nseg * st);
+  g.traces = take((size_t)steps * S * (size_t)R * w);
+  g.rec_p = take(5 * (size_t)g.C * S * K * Np * w);
+  g.rec_j = take(5 * (size_t)g.C * S * K * 8 * Nfp * w);
+  g.rb = take(st);
+  g.qb = take(st);
+  g.z = take(2 * S * K * 8 * Nfp * w);
+  g.gk = take(S * K * sizeof(double));
+  g.gt = take(S * K * 4 * sizeof(double));
+  g.total = off;
+  return g;
+}
+
+// Forward misfit run (checkpoints, traces, J) and, with grad != NULL, the
+// reverse sweep (see bb_adjoint.hip) and the gradient.
+template <typename T>
+int misfit_typed(bbdg_solver* s, int64_t shots, const T* q0, const int32_t* src_elem, const T* src_coef, double f0,
+                 double ts, int R, const int32_t* rec_elem, const T* rec_coef, const T* obs, double t0, double dt,
+                 int64_t steps, int64_t ckpt_every, double* J, double* grad, bool forward, char* work,
+                 hipStream_t st) {
+  const GradLayout L = grad_layout(s, shots, R, steps, ckpt_every);
+  const int Np = np_of(s->N), Nfp = nfp_of(s->N);
+  const int64_t n = shots * 4 * s->K * (int64_t)Np;
+  const size_t sbytes = (size_t)n * sizeof(T);
+  T* qs = (T*)(work + L.state);
+  T* fwork = (T*)(work + L.fwork);
+  T* ckpt = (T*)(work + L.ckpt);
+  T* traces = (T*)(work + L.traces);
+  const int wpb = (s->tuned_shots == shots && s->tuned_wpb) ? s->tuned_wpb : 4;
+  if (forward) {
+    if (q0) {
+      if (hipMemcpyAsync(qs, q0, sbytes, hipMemcpyDeviceToDevice, st) != hipSuccess) return BBDG_E_DEVICE;
+    } else if (hipMemsetAsync(qs, 0, sbytes, st) != hipSuccess) {
+      return BBDG_E_DEVICE;
+    }
+    for (int64_t seg = 0; seg < L.nseg; ++seg) {
+      const int64_t ns = std::min(L.C, steps - seg * L.C);
+      if (hipMemcpyAsync(ckpt + seg * n, qs, sbytes, hipMemcpyDeviceToDevice, st) != hipSuccess) return BBDG_E_DEVICE;
+      const int rc = run_batched_typed<T>(s, qs, shots, src_elem, src_coef, f0, ts, R, rec_elem, rec_coef,
+                                          traces + seg * L.C * shots * R, fwork, t0 + (double)(seg * L.C) * dt, dt,
+                                          ns, wpb, st);
+      if (rc != BBDG_OK) return rc;
+    }
+    const hipError_t le = launch_misfit<T>(steps * shots * R, traces, obs, J, st);
+    if (le != hipSuccess) return hip_fail(le, BBDG_E_LAUNCH);
+  }
+  if (!grad) return BBDG_OK;
+
+  T* rec_p = (T*)(work + L.rec_p);
+  T* rec_j = (T*)(work + L.rec_j);
+  T* rb = (T*)(work + L.rb);
+  T* qb = (T*)(work + L.qb);
+  T* z[2] = {(T*)(work + L.z), (T*)(work + L.z) + shots * s->K * 8 * Nfp};
+  double* gk = (double*)(work + L.gk);
+  double* gt = (double*)(work + L.gt);
+  if (hipMemsetAsync(rb, 0, sbytes, st) != hipSuccess || hipMemsetAsync(qb, 0, sbytes, st) != hipSuccess ||
+      hipMemsetAsync(gk, 0, (size_t)(shots * s->K) * sizeof(double), st) != hipSuccess ||
+      hipMemsetAsync(gt, 0, (size_t)(shots * s->K * 4) * sizeof(double), st) != hipSuccess)
+    return BBDG_E_DEVICE;
+  int cur = 0;
+  bool first = true;
+  for (int64_t seg = L.nseg - 1; seg >= 0; --seg) {
+    const int64_t ns = std::min(L.C, steps - seg * L.C);
+    // recompute the segment from its checkpoint, recording every stage
+    if (hipMemcpyAsync(qs, ckpt + seg * n, sbytes, hipMemcpyDeviceToDevice, st) != hipSuccess) return BBDG_E_DEVICE;
+    StageArgs<T> a = base_args<T>(s);
+    a.qin = qs;
+    a.qout = qs;
+    a.res = fwork;
+    a.qalt = fwork + n;
+    a.shots = shots;
+    a.nstages = 5 * ns;
+    a.t0 = t0 + (double)(seg * L.C) * dt;
+    a.dtd = dt;
+    a.src_elem = src_elem;
+    a.src_coef = src_coef;
+    a.f0 = f0;
+    a.tshift = ts;
+    a.rec_p = rec_p;
+    a.rec_j = rec_j;
+    const hipError_t e = launch_batched<T>(s->N, wpb, a, st);
+    if (e == hipErrorCooperativeLaunchTooLarge || e == hipErrorInvalidConfiguration) return hip_fail(e, BBDG_E_RESIDENT);
+    if (e != hipSuccess) return hip_fail(e, BBDG_E_LAUNCH);
+    for (int64_t it = ns - 1; it >= 0; --it) {
+      const int64_t step = seg * L.C + it;
+      const hipError_t le = launch_inject_receivers<T>(Np, s->K, shots, R, rec_elem, rec_coef,
+                                                       traces + step * shots * R, obs + step * shots * R, qb, st);
+      if (le != hipSuccess) return hip_fail(le, BBDG_E_LAUNCH);
+      for (int s5 = 4; s5 >= 0; --s5) {
+        AdjointArgs<T> ad{};
+        ad.rb = rb;
+        ad.qb = qb;
+        ad.z_in = z[cur ^ 1];
+        ad.z_out = z[cur];
+        ad.rec_p = rec_p + (5 * it + s5) * n / 4;
+        ad.rec_j = rec_j + (5 * it + s5) * shots * s->K * 8 * Nfp;
+        ad.gk = gk;
+        ad.gt = gt;
+        ad.geo = s->d_geo;
+        ad.etoe = s->d_etoe;
+        ad.etofo = s->d_etofo;
+        ad.tab = s->d_tab;
+        ad.K = s->K;
+        ad.shots = shots;
+        ad.a_s = (T)kRkA[s5];
+        ad.b_s = (T)kRkB[s5];
+        ad.dt = (T)dt;
+        ad.pull = first ? 0 : 1;
+        ad.bc = s->bc;
+        const hipError_t le = launch_adjoint_stage<T>(s->N, ad, st);
+        if (le != hipSuccess) return hip_fail(le, BBDG_E_LAUNCH);
+        first = false;
+        cur ^= 1;
+      }
+    }
+  }
+  const hipError_t le = launch_gradient_finalize(s->K, shots, s->d_geo, s->d_etoe, s->d_etofo, gk, gt, grad, st);
+  if (le != hipSuccess) return hip_fail(le, BBDG_E_LAUNCH);
+  return BBDG_OK;
 }
 }  // namespace
 
@@ -623,6 +778,34 @@ int bbdg_mesh_geometry(int64_t K, int64_t Nv, const double* VX, const int32_t* E
   return BBDG_OK;
 }
 
+// Per-element device header (kGeoStride doubles): grad lambda_1..3, kappa,
+// and per face the upwind weights a_p = kappa |g|/(c + c+) and
+// b_u = (c + c+)/(4 |g|), |g| = 2 |grad lambda_f| (c+ = c on the boundary).
+static void device_header(bbdg_solver* s, const double* c, std::vector<double>& dgeo) {
+  const int64_t K = s->K;
+  const double* geo = s->h_geo.data();
+  const int32_t* EToE = s->h_etoe.data();
+  dgeo.assign((size_t)(kGeoStride * K), 0.0);
+  s->h_kappa.resize((size_t)K);
+  for (int64_t k = 0; k < K; ++k) {
+    s->h_kappa[(size_t)k] = c[k] * c[k];
+    double* o = dgeo.data() + (size_t)(kGeoStride * k);
+    for (int i = 0; i < 9; ++i) o[i] = geo[10 * k + i];
+    o[9] = c[k] * c[k];
+    for (int f = 0; f < 4; ++f) {
+      const int64_t slot = 4 * k + f;
+      // grad lambda_f (lambda_0 = 1 - lambda_1 - lambda_2 - lambda_3)
+      double gl[3];
+      for (int d = 0; d < 3; ++d)
+        gl[d] = f == 0 ? -(geo[10 * k + d] + geo[10 * k + 3 + d] + geo[10 * k + 6 + d]) : geo[10 * k + 3 * (f - 1) + d];
+      const double gn = 2.0 * std::sqrt(gl[0] * gl[0] + gl[1] * gl[1] + gl[2] * gl[2]);
+      const double cp = EToE[slot] >= 0 ? c[EToE[slot]] : c[k];
+      o[10 + f] = c[k] * c[k] * gn / (c[k] + cp);  // kappa tau_p |g| / 2
+      o[14 + f] = (c[k] + cp) / (4.0 * gn);         // tau_u / (2 |g|)
+    }
+  }
+}
+
 static int create_impl(bbdg_solver** out, int N, int dtype, int64_t K, const int32_t* EToE, const int8_t* EToF,
                        const int8_t* EToO, const double* geo, const double* c, int bc, int device, int basis) {
   if (!out) return BBDG_E_ARG;
@@ -658,32 +841,15 @@ static int create_impl(bbdg_solver** out, int N, int dtype, int64_t K, const int
   s->device = device;
   s->K = K;
   s->basis = basis;
+  s->h_geo.assign(geo, geo + 10 * K);
+  s->h_etoe.assign(EToE, EToE + 4 * K);
   s->h_J.resize((size_t)K);
-  s->h_kappa.resize((size_t)K);
-  for (int64_t k = 0; k < K; ++k) {
-    s->h_J[(size_t)k] = geo[10 * k + 9];
-    s->h_kappa[(size_t)k] = c[k] * c[k];
-  }
-
-  std::vector<double> dgeo((size_t)(kGeoStride * K));
+  for (int64_t k = 0; k < K; ++k) s->h_J[(size_t)k] = geo[10 * k + 9];
+  std::vector<double> dgeo;
+  device_header(s, c, dgeo);
   std::vector<uint8_t> fo((size_t)(4 * K));
-  for (int64_t k = 0; k < K; ++k) {
-    double* o = dgeo.data() + (size_t)(kGeoStride * k);
-    for (int i = 0; i < 9; ++i) o[i] = geo[10 * k + i];
-    o[9] = c[k] * c[k];
-    for (int f = 0; f < 4; ++f) {
-      const int64_t slot = 4 * k + f;
-      fo[(size_t)slot] = EToE[slot] >= 0 ? (uint8_t)((EToF[slot] & 3) | (EToO[slot] << 2)) : 0;
-      // grad lambda_f (lambda_0 = 1 - lambda_1 - lambda_2 - lambda_3)
-      double gl[3];
-      for (int d = 0; d < 3; ++d)
-        gl[d] = f == 0 ? -(geo[10 * k + d] + geo[10 * k + 3 + d] + geo[10 * k + 6 + d]) : geo[10 * k + 3 * (f - 1) + d];
-      const double gn = 2.0 * std::sqrt(gl[0] * gl[0] + gl[1] * gl[1] + gl[2] * gl[2]);
-      const double cp = EToE[slot] >= 0 ? c[EToE[slot]] : c[k];
-      o[10 + f] = c[k] * c[k] * gn / (c[k] + cp);  // kappa tau_p |g| / 2
-      o[14 + f] = (c[k] + cp) / (4.0 * gn);         // tau_u / (2 |g|)
-    }
-  }
+  for (int64_t slot = 0; slot < 4 * K; ++slot)
+    fo[(size_t)slot] = EToE[slot] >= 0 ? (uint8_t)((EToF[slot] & 3) | (EToO[slot] << 2)) : 0;
   const std::vector<uint16_t> tab = build_tables(N);
   bool ok = hipMalloc(&s->d_geo, dgeo.size() * sizeof(double)) == hipSuccess &&
             hipMalloc(&s->d_etoe, (size_t)(4 * K) * sizeof(int32_t)) == hipSuccess &&
@@ -769,7 +935,7 @@ int bbdg_rhs(bbdg_solver* s, const void* q, void* rhs, int mode, void* stream) {
     e = launch_any<double>(s, km, (const double*)q, (double*)rhs, nullptr, 0.0, 0.0, 0.0, 0, st);
   else
     e = launch_any<float>(s, km, (const float*)q, (float*)rhs, nullptr, 0.f, 0.f, 0.f, 0, st);
-  return e == hipSuccess ? BBDG_OK : BBDG_E_LAUNCH;
+  return e == hipSuccess ? BBDG_OK : hip_fail(e, BBDG_E_LAUNCH);
 }
 
 size_t bbdg_work_bytes(const bbdg_solver* s) {
@@ -954,6 +1120,64 @@ int bbdg_tune_batched(bbdg_solver* s, int64_t shots, void* scratch, int* wpb, vo
   *wpb = best;
   return BBDG_OK;
 }
+
+int bbdg_set_wavespeed(bbdg_solver* s, const double* c) {
+  if (!s || !c) return BBDG_E_ARG;
+  if (!finite_all(c, s->K)) return BBDG_E_NONFINITE;
+  for (int64_t k = 0; k < s->K; ++k)
+    if (!(c[k] > 0.0)) return BBDG_E_ARG;
+  std::vector<double> dgeo;
+  device_header(s, c, dgeo);
+  if (hipSetDevice(s->device) != hipSuccess) return BBDG_E_DEVICE;
+  if (hipDeviceSynchronize() != hipSuccess) return BBDG_E_DEVICE;
+  if (hipMemcpy(s->d_geo, dgeo.data(), dgeo.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+    return BBDG_E_DEVICE;
+  return BBDG_OK;
+}
+
+size_t bbdg_misfit_work_bytes(const bbdg_solver* s, int64_t shots, int R, int64_t steps, int64_t ckpt_every) {
+  if (!s || !batched_shape_ok(s, shots) || R < 0 || steps < 1) return 0;
+  return grad_layout(s, shots, R, steps, ckpt_every).total;
+}
+
+static int misfit_entry(bbdg_solver* s, int64_t shots, const void* q0, const int32_t* src_elem, const void* src_coef,
+                        double f0, double ts, int R, const int32_t* rec_elem, const void* rec_coef, const void* obs,
+                        double t0, double dt, int64_t steps, int64_t ckpt_every, double* J, double* grad,
+                        bool forward, void* work, void* stream) {
+  if (!s || s->basis != 0 || !work || !obs || steps < 1 || R < 1 || !rec_elem || !rec_coef) return BBDG_E_ARG;
+  if (forward && !J) return BBDG_E_ARG;
+  if (!forward && !grad) return BBDG_E_ARG;
+  if (!batched_shape_ok(s, shots) || (src_elem && !src_coef)) return BBDG_E_ARG;
+  if (!std::isfinite(t0) || !std::isfinite(dt) || !std::isfinite(f0) || !std::isfinite(ts)) return BBDG_E_NONFINITE;
+  if (src_elem && !(f0 > 0.0)) return BBDG_E_ARG;
+  if (((uintptr_t)work) % 256 != 0) return BBDG_E_ARG;
+  if (hipSetDevice(s->device) != hipSuccess) return BBDG_E_DEVICE;
+  hipStream_t st = (hipStream_t)stream;
+  if (s->dtype == BBDG_F64)
+    return misfit_typed<double>(s, shots, (const double*)q0, src_elem, (const double*)src_coef, f0, ts, R, rec_elem,
+                                (const double*)rec_coef, (const double*)obs, t0, dt, steps, ckpt_every, J, grad,
+                                forward, (char*)work, st);
+  return misfit_typed<float>(s, shots, (const float*)q0, src_elem, (const float*)src_coef, f0, ts, R, rec_elem,
+                             (const float*)rec_coef, (const float*)obs, t0, dt, steps, ckpt_every, J, grad, forward,
+                             (char*)work, st);
+}
+
+int bbdg_misfit(bbdg_solver* s, int64_t shots, const void* q0, const int32_t* src_elem, const void* src_coef, double f0,
+                double ts, int R, const int32_t* rec_elem, const void* rec_coef, const void* obs, double t0, double dt,
+                int64_t steps, int64_t ckpt_every, double* J, void* work, void* stream) {
+  return misfit_entry(s, shots, q0, src_elem, src_coef, f0, ts, R, rec_elem, rec_coef, obs, t0, dt, steps,
+                      ckpt_every, J, nullptr, true, work, stream);
+}
+
+int bbdg_misfit_gradient(bbdg_solver* s, int64_t shots, const void* q0, const int32_t* src_elem, const void* src_coef,
+                         double f0, double ts, int R, const int32_t* rec_elem, const void* rec_coef, const void* obs,
+                         double t0, double dt, int64_t steps, int64_t ckpt_every, double* grad, void* work,
+                         void* stream) {
+  return misfit_entry(s, shots, q0, src_elem, src_coef, f0, ts, R, rec_elem, rec_coef, obs, t0, dt, steps,
+                      ckpt_every, nullptr, grad, false, work, stream);
+}
+
+int bbdg_last_hip_error(void) { return g_last_hip_error; }
 
 int bbdg_copy_probe(const void* src, void* dst, size_t bytes, void* stream) {
   if (!src || !dst || bytes % 16 != 0) return BBDG_E_ARG;

@@ -32,6 +32,7 @@ hipError_t launch_copy_probe(const void* src, void* dst, size_t bytes, hipStream
   if (n <= 0) return hipSuccess;
   const int64_t blocks = (n + 1023) / 1024;
   if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+  (void)hipGetLastError();  // drop errors left by earlier, unrelated calls
   hipLaunchKernelGGL(copy_probe_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, (const u32x4*)src, (u32x4*)dst, n);
   return hipGetLastError();
 }

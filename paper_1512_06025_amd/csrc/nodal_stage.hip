@@ -302,6 +302,7 @@ static hipError_t nodal_launch_one(const NodalArgs<T>& a, hipStream_t stream) {
   if (grid > ((needed + 7) / 8) * 8) grid = ((needed + 7) / 8) * 8;
   grid = ((grid + 7) / 8) * 8;
   if (grid < 8) grid = 8;
+  (void)hipGetLastError();  // drop errors left by earlier, unrelated calls
   hipLaunchKernelGGL((nodal_stage_kernel<N, T, MODE>), dim3((unsigned)grid), dim3(64 * WPB), 0, stream, a);
   return hipGetLastError();
 }

@@ -1,5 +1,6 @@
 """Torch-facing wrapper of libbbdg: marshals arrays and tensors into the C ABI."""
 import ctypes
+import functools
 
 import numpy as np
 
@@ -176,15 +177,14 @@ class BatchedSolver:
         self.wpb = int(wpb)
         dev = s.device
         self.src_elem = self.src_coef = None
+        self._src = None
         if sources is not None:
             elem, bary = locate_points(mesh, sources)
             if elem.shape[0] != self.S:
                 raise ValueError("need one source per shot")
-            coef = np.zeros((self.S, s.Np))
-            check(load().bbdg_source_coeffs(s._h, self.S, elem.ctypes.data, bary.ctypes.data, coef.ctypes.data),
-                  "bbdg_source_coeffs")
+            self._src = (elem, bary)
             self.src_elem = torch.from_numpy(elem).to(dev)
-            self.src_coef = torch.from_numpy(coef).to(dev, s.torch_dtype)
+            self.update_sources()
         self.R = 0
         self.rec_elem = self.rec_coef = None
         if receivers is not None and len(receivers):
@@ -193,6 +193,18 @@ class BatchedSolver:
             self.rec_elem = torch.from_numpy(elem).to(dev)
             self.rec_coef = torch.from_numpy(bernstein_eval(N, bary)).to(dev, s.torch_dtype)
         self._work = None
+
+    def update_sources(self):
+        """(Re)computes the source vectors, which scale with kappa of the source element."""
+        import torch
+        if self._src is None:
+            return
+        s = self.solver
+        elem, bary = self._src
+        coef = np.zeros((self.S, s.Np))
+        check(load().bbdg_source_coeffs(s._h, self.S, elem.ctypes.data, bary.ctypes.data, coef.ctypes.data),
+              "bbdg_source_coeffs")
+        self.src_coef = torch.from_numpy(coef).to(s.device, s.torch_dtype)
 
     def empty_state(self):
         import torch
@@ -244,3 +256,89 @@ class BatchedSolver:
 
     def close(self):
         self.solver.close()
+
+
+class Misfit:
+    """Receiver misfit J(m) = 1/2 sum (d(m) - d_obs)^2 of a batched forward run
+    and its gradient in m = c^2 per element (discrete adjoint on the GPU).
+
+    d_obs: CUDA tensor (steps, S, R) of the solver's element type.  evaluate(m)
+    sets the wavespeed to sqrt(m), runs the forward problem keeping
+    checkpoints every ckpt_every steps, and returns J (0-dim float64 CUDA
+    tensor); gradient() then returns dJ/dm (K,) float64 for that m."""
+
+    def __init__(self, N, mesh, m, shots, sources, receivers, d_obs, dt, steps, t0=0.0, f0=8.0, ts=0.125,
+                 ckpt_every=0, dtype="f32", bc="rigid", device=0):
+        import torch
+        m = np.asarray(m, dtype=np.float64)
+        self.batched = BatchedSolver(N, mesh, np.sqrt(m), shots, sources=sources, receivers=receivers, f0=f0,
+                                     ts=ts, dtype=dtype, bc=bc, device=device, wpb=4)
+        s = self.batched.solver
+        self.dt, self.steps, self.t0, self.ckpt = float(dt), int(steps), float(t0), int(ckpt_every)
+        self.d_obs = d_obs.to(s.device, s.torch_dtype).contiguous()
+        if tuple(self.d_obs.shape) != (self.steps, self.batched.S, self.batched.R):
+            raise ValueError("d_obs must be (steps, shots, receivers)")
+        nbytes = load().bbdg_misfit_work_bytes(s._h, self.batched.S, self.batched.R, self.steps, self.ckpt)
+        if nbytes == 0:
+            raise ValueError("invalid misfit sizes")
+        self._work = torch.empty(nbytes // 8 + 32, dtype=torch.float64, device=s.device)
+        self._J = torch.zeros((), dtype=torch.float64, device=s.device)
+        self._evaluated = False
+
+    def _args(self):
+        b = self.batched
+
+        def ptr(t):
+            return ctypes.c_void_p(t.data_ptr() if t is not None else None)
+        return (b.solver._h, b.S, ctypes.c_void_p(None), ptr(b.src_elem), ptr(b.src_coef), b.f0, b.ts, b.R,
+                ptr(b.rec_elem), ptr(b.rec_coef), ptr(self.d_obs), self.t0, self.dt, self.steps, self.ckpt)
+
+    def set_m(self, m):
+        import torch
+        mh = m.detach().to("cpu", torch.float64).numpy() if isinstance(m, torch.Tensor) else np.asarray(m, np.float64)
+        c = np.ascontiguousarray(np.sqrt(mh))
+        check(load().bbdg_set_wavespeed(self.batched.solver._h, c.ctypes.data), "bbdg_set_wavespeed")
+        self.batched.update_sources()
+
+    def evaluate(self, m=None, stream=None):
+        if m is not None:
+            self.set_m(m)
+        check(load().bbdg_misfit(*self._args(), ctypes.c_void_p(self._J.data_ptr()),
+                                 ctypes.c_void_p(self._work.data_ptr()), _stream_ptr(stream)), "bbdg_misfit")
+        self._evaluated = True
+        return self._J.clone()
+
+    def gradient(self, stream=None):
+        import torch
+        if not self._evaluated:
+            raise RuntimeError("evaluate() first")
+        g = torch.empty(self.batched.solver.K, dtype=torch.float64, device=self.batched.solver.device)
+        check(load().bbdg_misfit_gradient(*self._args(), ctypes.c_void_p(g.data_ptr()),
+                                          ctypes.c_void_p(self._work.data_ptr()), _stream_ptr(stream)),
+              "bbdg_misfit_gradient")
+        return g
+
+    def close(self):
+        self.batched.close()
+
+
+@functools.lru_cache(maxsize=None)
+def _misfit_function():
+    import torch
+
+    class MisfitFunction(torch.autograd.Function):
+        """J = MisfitFunction.apply(m, misfit): forward runs the forward
+        problem (checkpointed); backward runs the adjoint sweep, which
+        recomputes each segment from its checkpoint, and returns
+        grad_output * dJ/dm."""
+
+        @staticmethod
+        def forward(ctx, m, misfit):
+            ctx.misfit = misfit
+            return misfit.evaluate(m)
+
+        @staticmethod
+        def backward(ctx, grad_out):
+            return grad_out * ctx.misfit.gradient(), None
+
+    return MisfitFunction

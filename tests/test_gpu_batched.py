@@ -134,7 +134,9 @@ def test_c4_full_size_sampled():
         want, wtr = prob.run_shots(np.zeros((1, 4, prob.K, prob.Np)), dt, steps, se[s:s + 1], sl[s:s + 1],
                                    cfg["f0"], cfg["ts"], re, rl, t0=t0)
         assert _rel(qh[s], want[0]) < 1e-5, s
-        assert _rel(_host(tr)[:, s], wtr[:, 0]) < 1e-5, s
+        # the receivers (z = 0.9) may not have been reached yet: compare absolutely
+        got_tr = _host(tr)[:, s]
+        assert np.abs(got_tr - wtr[:, 0]).max() <= 1e-5 * max(np.abs(wtr).max(), 1e-5 * np.abs(want[0][0]).max())
     # conservation for every shot
     I_res = 0.0
     I = 0.0

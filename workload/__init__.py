@@ -126,8 +126,11 @@ PRESETS = {
     # delay 1/f0, seeded positions in [0.1, 0.9]^3), 8 x 8 receivers on
     # z = 0.9, zero initial state, 500 steps
     "c4": dict(n=16, jitter=0.0, N=4, c=(1.0, 3.0), ic="zero", steps=500, shots=64, f0=8.0, ts=0.125),
-    # 24,576 tets, N=5, adjoint workload, 500 steps
-    "c5": dict(n=16, jitter=0.0, N=5, c=(1.0, 1.0), ic="zero", steps=500),
+    # 24,576 tets, N=5, misfit gradient: 8 shots with Ricker sources on the
+    # plane z = 0.9, 8 x 8 receivers on the same plane, observations from the
+    # blob model m_true, gradient at m = 1, 500 steps, checkpoints every 50
+    "c5": dict(n=16, jitter=0.0, N=5, c=(1.0, 1.0), ic="zero", steps=500, shots=8, f0=8.0, ts=0.125,
+               ckpt_every=50),
 }
 
 
@@ -164,6 +167,19 @@ def receiver_grid(m=8, z=0.9, lo=0.1, hi=0.9):
     return np.stack([X.ravel(), Y.ravel(), np.full(m * m, z)], axis=1)
 
 
+def plane_sources(S, z=0.9, seed=SEED_SOURCES, lo=0.1, hi=0.9):
+    """(S, 3) source positions uniform in [lo, hi]^2 on the plane z."""
+    xy = np.random.default_rng(seed).uniform(lo, hi, (S, 2))
+    return np.concatenate([xy, np.full((S, 1), z)], axis=1)
+
+
+def blob_model(VX, EToV, centre=(0.5, 0.5, 0.75), amp=0.5, width=100.0):
+    """m = c^2 per element: 1 + amp exp(-width |x_k - centre|^2) at the element centroids."""
+    cen = np.asarray(VX)[np.asarray(EToV)].mean(axis=1)
+    r2 = np.sum((cen - np.asarray(centre)) ** 2, axis=1)
+    return 1.0 + amp * np.exp(-width * r2)
+
+
 def element_count(n, drop_last=0):
     return 6 * n ** 3 - drop_last
 
@@ -171,5 +187,5 @@ def element_count(n, drop_last=0):
 __all__ = [
     "kuhn_cube_mesh", "wavespeed", "random_coeffs", "standing_mode_p0",
     "gaussian_pulse_p0", "INITIAL_FIELDS", "PRESETS", "preset", "build_preset",
-    "nodes_per_element", "element_count", "source_positions", "receiver_grid",
+    "nodes_per_element", "element_count", "source_positions", "receiver_grid", "plane_sources", "blob_model",
 ]
