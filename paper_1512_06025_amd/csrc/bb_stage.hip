@@ -49,37 +49,68 @@
 
 namespace bbdg {
 
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-}
+// The two lifted vectors of a face (pressure flux, velocity flux) share every
+// index and weight of L_0 and of the reductions, so they are stored and
+// processed as one pair per position.
+template <typename T>
+struct alignas(2 * sizeof(T)) Pair {
+  T p, u;
+};
 
 template <int N, typename T>
 struct Shape {
   static constexpr int Np = np_of(N);
   static constexpr int Nfp = nfp_of(N);
-  static constexpr int E = (Np <= 32) ? (64 / Np) : 1;    // elements per wave group
-  static constexpr int NPL = (E * Np + 63) / 64;          // nodes per lane
-  static constexpr int NFI = (E * 4 * Nfp + 63) / 64;     // face items per lane
-  // faces per lift batch (bounds the LDS of the face vectors)
-  static constexpr int FB = sizeof(T) == 8 ? (N >= 8 ? 1 : (N >= 6 ? 2 : 4)) : (N >= 8 ? 2 : 4);
-  static constexpr int NV = 2 * FB;
-  static constexpr int HG = E * kGeoStride;               // header doubles per wave
-  static constexpr int NHG = (HG + 63) / 64;
-  static constexpr int NHE = (E * 4 + 63) / 64;
+  static constexpr int E = (Np <= 32) ? (64 / Np) : 1;    // elements per group
+  // waves that share one element group in the single-stage kernel (the whole
+  // workgroup when > 1); batched launches always use one wave per group
+  static constexpr int TW = sizeof(T) == 8 ? (N >= 8 ? 4 : 1) : 1;
+  // faces per lift batch (bounds the LDS of the face vectors), for one-wave
+  // teams and for workgroup teams
+  static constexpr int FB1 = sizeof(T) == 8 ? (N >= 8 ? 1 : (N >= 6 ? 2 : 4)) : (N >= 8 ? 2 : 4);
+  static constexpr int FBT = 2;
+  static constexpr int HG = E * kGeoStride;               // header doubles per group
   // per-element derived geometry (type T): grad lambda_0..3 (12), kappa, pad,
   // then per face f at 16 + 8 f: g_x, g_y, g_z, a_p, a_u, b_u, pad, pad with
   //   sp = a_p [[p]] - a_u g.[[u]],  su = b_u g.[[u]] - [[p]]/2.
   static constexpr int GEO = 48;
+  // register-lean variant for high orders: the LSRK residual is loaded after
+  // the volume term and the own coefficients are re-read from LDS at the update
+  static constexpr bool LATE_RES = sizeof(T) == 8 ? (N >= 6) : (N >= 8);
 };
 
+// Per-thread counts for a team of TW waves (TPE threads) working on one group.
+template <int N, typename T, int TW>
+struct Team {
+  using S = Shape<N, T>;
+  static constexpr int TPE = 64 * TW;
+  static constexpr int NPL = (S::E * S::Np + TPE - 1) / TPE;      // nodes per thread
+  static constexpr int NFI = (S::E * 4 * S::Nfp + TPE - 1) / TPE;  // face items per thread
+  static constexpr int NHG = (S::HG + TPE - 1) / TPE;
+  static constexpr int NHE = (S::E * 4 + TPE - 1) / TPE;
+};
+
+// Synchronisation of the threads that share an element group.  LDS operations
+// of a wavefront complete in issue order, so for a one-wave team an LDS-only
+// fence plus a wave barrier suffices; larger teams add a workgroup barrier.
+// Neither waits for global loads in flight.
+template <int TW>
+__device__ __forceinline__ void team_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  if constexpr (TW > 1) {
+    __builtin_amdgcn_s_barrier();
+  } else {
+    __builtin_amdgcn_wave_barrier();
+  }
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Occupancy target (waves per SIMD) that bounds the register allocation.
-template <int N, typename T>
+template <int N, typename T, int TW>
 struct Occ {
-  static constexpr int f64[10] = {0, 3, 3, 4, 4, 4, 3, 2, 2, 2};
-  static constexpr int f32[10] = {0, 4, 4, 5, 5, 5, 4, 4, 3, 2};
-  static constexpr int value = sizeof(T) == 8 ? f64[N] : f32[N];
+  static constexpr int f64[10] = {0, 2, 3, 4, 4, 4, 3, 3, 2, 2};
+  static constexpr int f32[10] = {0, 3, 4, 5, 5, 5, 4, 4, 3, 3};
+  static constexpr int value = TW > 1 ? 4 : (sizeof(T) == 8 ? f64[N] : f32[N]);
 };
 
 template <int N>
@@ -93,27 +124,28 @@ struct Ell {
   static constexpr double value(int j) { return ((j & 1) ? -1.0 : 1.0) * binom(N, j) / (1.0 + j); }
 };
 
-template <int N, typename T>
+template <int N, typename T, int TW>
 struct Header {
-  double geo[Shape<N, T>::NHG];
-  int32_t etoe[Shape<N, T>::NHE];
-  uint32_t fo[Shape<N, T>::NHE];
+  double geo[Team<N, T, TW>::NHG];
+  int32_t etoe[Team<N, T, TW>::NHE];
+  uint32_t fo[Team<N, T, TW>::NHE];
 };
 
-template <int N, typename T>
-__device__ __forceinline__ void load_header(Header<N, T>& h, const StageArgs<T>& A, int64_t g, int lane) {
+template <int N, typename T, int TW>
+__device__ __forceinline__ void load_header(Header<N, T, TW>& h, const StageArgs<T>& A, int64_t g, int tl) {
   using S = Shape<N, T>;
+  using M = Team<N, T, TW>;
   const int64_t e0 = g * S::E;
 #pragma unroll
-  for (int r = 0; r < S::NHG; ++r) {
-    const int v = lane + 64 * r;
+  for (int r = 0; r < M::NHG; ++r) {
+    const int v = tl + M::TPE * r;
     int64_t idx = e0 * kGeoStride + v;
     if (v >= S::HG || idx >= A.K * kGeoStride) idx = 0;
     h.geo[r] = A.geo[idx];
   }
 #pragma unroll
-  for (int r = 0; r < S::NHE; ++r) {
-    const int v = lane + 64 * r;
+  for (int r = 0; r < M::NHE; ++r) {
+    const int v = tl + M::TPE * r;
     int64_t idx = e0 * 4 + v;
     if (v >= S::E * 4 || idx >= A.K * 4) idx = 0;
     h.etoe[r] = A.etoe[idx];
@@ -150,12 +182,16 @@ __device__ __forceinline__ double ricker(double t, double f0, double tshift) {
 }
 
 template <int N, typename T, int MODE, int WPB>
-__global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(Occ<N, T>::value)))
+__global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(Occ<N, T, (MODE == kBatched ? 1 : Shape<N, T>::TW)>::value)))
 void bb_stage_kernel(StageArgs<T> A) {
   using S = Shape<N, T>;
-  constexpr int Np = S::Np, Nfp = S::Nfp, E = S::E, NPL = S::NPL, NFI = S::NFI;
-  constexpr int FB = S::FB, NV = S::NV, GEO = S::GEO;
   constexpr bool kBatch = (MODE == kBatched);
+  constexpr int TW = kBatch ? 1 : S::TW;  // waves per element team
+  static_assert(WPB % TW == 0 && (TW == 1 || TW == WPB), "a team is one wave or the whole workgroup");
+  using M = Team<N, T, TW>;
+  constexpr int TEAMS = WPB / TW, TPE = M::TPE;
+  constexpr int Np = S::Np, Nfp = S::Nfp, E = S::E, NPL = M::NPL, NFI = M::NFI;
+  constexpr int FB = TW > 1 ? S::FBT : S::FB1, GEO = S::GEO;
   constexpr bool kUpdate = (MODE == kStage || MODE == kBatched);
   constexpr int PK = sizeof(T) == 4 ? 4 : 1;
   constexpr bool kVol = (MODE != kRhsSurface);
@@ -178,13 +214,13 @@ void bb_stage_kernel(StageArgs<T> A) {
   // per-wave buffers
   // the element's coefficients, field-major in double, (p,u,v,w) packed into
   // one 16-byte vector per node in float
-  __shared__ __attribute__((aligned(16))) T sq[WPB][E][4 / PK][Np][PK];
-  __shared__ __attribute__((aligned(16))) T sfl[WPB][E][NV][Nfp];
-  __shared__ __attribute__((aligned(16))) T slev[WPB][E][NV][Np];
-  __shared__ __attribute__((aligned(16))) T sgeo[WPB][E][GEO];
-  __shared__ double shg[WPB][E * kGeoStride];
-  __shared__ int32_t she[WPB][E * 4];
-  __shared__ uint8_t shf[WPB][E * 4];
+  __shared__ __attribute__((aligned(16))) T sq[TEAMS][E][4 / PK][Np][PK];
+  __shared__ Pair<T> sfl[TEAMS][E][FB][Nfp];
+  __shared__ Pair<T> slev[TEAMS][E][FB][Np];
+  __shared__ __attribute__((aligned(16))) T sgeo[TEAMS][E][GEO];
+  __shared__ double shg[TEAMS][E * kGeoStride];
+  __shared__ int32_t she[TEAMS][E * 4];
+  __shared__ uint8_t shf[TEAMS][E * 4];
 
   const int tid = threadIdx.x;
   for (int i = tid; i < 24 * Nfp; i += 64 * WPB) t_nbr[i] = A.tab[L.nbrnode + i];
@@ -234,8 +270,8 @@ void bb_stage_kernel(StageArgs<T> A) {
   }
   __syncthreads();
 
-  const int lane0 = tid & 63;
-  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave index (uniform)
+  const int lane0 = tid % TPE;                              // thread within the team
+  const int w = __builtin_amdgcn_readfirstlane(tid / TPE);  // team index (uniform)
   const int64_t K = A.K;
   const int64_t KNp = K * Np;
   const int64_t G = (K + E - 1) / E;  // element groups per shot
@@ -243,7 +279,7 @@ void bb_stage_kernel(StageArgs<T> A) {
   // XCD-aware split of the element groups (gridDim.x is a multiple of 8)
   const int xcd = blockIdx.x & 7;
   const int64_t g_lo = GS * xcd / 8, g_hi = GS * (xcd + 1) / 8;
-  const int64_t wstride = (int64_t)(gridDim.x >> 3) * WPB;
+  const int64_t wstride = (int64_t)(gridDim.x >> 3) * TEAMS;
   const int64_t nst = kBatch ? A.nstages : 1;
 
   for (int64_t stage = 0; stage < nst; ++stage) {
@@ -256,10 +292,10 @@ void bb_stage_kernel(StageArgs<T> A) {
   const int read_res = kBatch ? (s5 != 0) : A.read_res;
   const T amp = kBatch ? (T)ricker(A.t0 + (double)(stage / 5) * A.dtd + kLsrkC[s5] * A.dtd, A.f0, A.tshift) : (T)0;
 
-  int64_t g = g_lo + (int64_t)(blockIdx.x >> 3) * WPB + w;
-  Header<N, T> hd;
+  int64_t g = g_lo + (int64_t)(blockIdx.x >> 3) * TEAMS + w;
+  Header<N, T, TW> hd;
   // group g = shot * G + element group (shots * G < 2^32 is checked on the host)
-  if (g < g_hi) load_header<N, T>(hd, A, kBatch ? (int64_t)((uint32_t)g % (uint32_t)G) : g, lane0);
+  if (g < g_hi) load_header<N, T, TW>(hd, A, kBatch ? (int64_t)((uint32_t)g % (uint32_t)G) : g, lane0);
 
   for (; g < g_hi; g += wstride) {
     const int64_t shot = kBatch ? (int64_t)((uint32_t)g / (uint32_t)G) : 0;
@@ -275,35 +311,35 @@ void bb_stage_kernel(StageArgs<T> A) {
     asm volatile("" : "+v"(lane));
 
     // ---- header of this group -> LDS --------------------------------------
-    wave_lds_sync();
+    team_sync<TW>();
 #pragma unroll
-    for (int r = 0; r < S::NHG; ++r) {
-      const int v = lane + 64 * r;
+    for (int r = 0; r < M::NHG; ++r) {
+      const int v = lane + TPE * r;
       if (v < S::HG) shg[w][v] = hd.geo[r];
     }
 #pragma unroll
-    for (int r = 0; r < S::NHE; ++r) {
-      const int v = lane + 64 * r;
+    for (int r = 0; r < M::NHE; ++r) {
+      const int v = lane + TPE * r;
       if (v < E * 4) {
         she[w][v] = hd.etoe[r];
         shf[w][v] = (uint8_t)hd.fo[r];
       }
     }
-    wave_lds_sync();
+    team_sync<TW>();
 
     // ---- issue this group's loads: own q, residual, neighbour traces --------
     T qv[NPL][4], rv[NPL][4];
     uint32_t noff[NPL];
 #pragma unroll
     for (int r = 0; r < NPL; ++r) {
-      const int v = lane + 64 * r;
+      const int v = lane + TPE * r;
       const int el = v / Np;
       const int n = v - el * Np;
       const bool ok = (v < E * Np) && (e0 + el < K);
       noff[r] = ok ? (uint32_t)((e0 + el) * Np + n) : 0u;
 #pragma unroll
       for (int f = 0; f < 4; ++f) qv[r][f] = ld(qin_f[f], noff[r]);
-      if (kUpdate && read_res) {
+      if (kUpdate && read_res && !S::LATE_RES) {
 #pragma unroll
         for (int f = 0; f < 4; ++f) rv[r][f] = ld(res_s + f * KNp, noff[r]);
       } else {
@@ -315,7 +351,7 @@ void bb_stage_kernel(StageArgs<T> A) {
     if constexpr (kSurf) {
 #pragma unroll
       for (int r = 0; r < NFI; ++r) {
-        const int v = lane + 64 * r;
+        const int v = lane + TPE * r;
         const int el = v / (4 * Nfp);
         const int rem = v - el * 4 * Nfp;
         const int f = rem / Nfp;
@@ -332,10 +368,10 @@ void bb_stage_kernel(StageArgs<T> A) {
     }
     // ---- prefetch the next group's header -----------------------------------
     if (g + wstride < g_hi)
-      load_header<N, T>(hd, A, kBatch ? (int64_t)((uint32_t)(g + wstride) % (uint32_t)G) : g + wstride, lane);
+      load_header<N, T, TW>(hd, A, kBatch ? (int64_t)((uint32_t)(g + wstride) % (uint32_t)G) : g + wstride, lane);
 
     // ---- per-element derived geometry (one lane per element face) ------------
-    for (int v = lane; v < E * 4; v += 64) {
+    for (int v = lane; v < E * 4; v += TPE) {
       const int el = v >> 2;
       const int f = v & 3;
       const double* ge = shg[w] + el * kGeoStride;
@@ -366,7 +402,7 @@ void bb_stage_kernel(StageArgs<T> A) {
     // ---- own coefficients -> LDS -----------------------------------------------
 #pragma unroll
     for (int r = 0; r < NPL; ++r) {
-      const int v = lane + 64 * r;
+      const int v = lane + TPE * r;
       if (v < E * Np) {
         const int el = v / Np;
         const int n = v - el * Np;
@@ -374,7 +410,7 @@ void bb_stage_kernel(StageArgs<T> A) {
         for (int f = 0; f < 4; ++f) sq[w][el][f / PK][n][f % PK] = qv[r][f];
       }
     }
-    wave_lds_sync();
+    team_sync<TW>();
 
     // ---- volume term ------------------------------------------------------------
     T rhs[NPL][4];
@@ -386,7 +422,7 @@ void bb_stage_kernel(StageArgs<T> A) {
     if constexpr (kVol) {
 #pragma unroll
       for (int r = 0; r < NPL; ++r) {
-        const int v = lane + 64 * r;
+        const int v = lane + TPE * r;
         if (v >= E * Np) continue;
         const int el = v / Np;
         const int n = v - el * Np;
@@ -435,6 +471,16 @@ void bb_stage_kernel(StageArgs<T> A) {
       }
     }
 
+    if constexpr (kUpdate && S::LATE_RES) {
+      if (read_res) {
+#pragma unroll
+        for (int r = 0; r < NPL; ++r) {
+#pragma unroll
+          for (int f = 0; f < 4; ++f) rv[r][f] = ld(res_s + f * KNp, noff[r]);
+        }
+      }
+    }
+
     // ---- surface term, FB faces at a time ------------------------------------------
     if constexpr (kSurf) {
 #pragma unroll
@@ -442,7 +488,7 @@ void bb_stage_kernel(StageArgs<T> A) {
         // flux on the face nodes of faces fb0 .. fb0+FB-1
 #pragma unroll
         for (int r = 0; r < NFI; ++r) {
-          const int v = lane + 64 * r;
+          const int v = lane + TPE * r;
           const int el = v / (4 * Nfp);
           const int rem = v - el * 4 * Nfp;
           const int f = rem / Nfp;
@@ -474,53 +520,57 @@ void bb_stage_kernel(StageArgs<T> A) {
               rj[Nfp] = jgu;
             }
           }
-          sfl[w][el][f - fb0][gg] = sp;
-          sfl[w][el][FB + f - fb0][gg] = su;
+          sfl[w][el][f - fb0][gg] = Pair<T>{sp, su};
         }
-        wave_lds_sync();
+        team_sync<TW>();
 
-        // w_0 = L_0 s, one row per (vector, position) item, position fastest
-        for (int v = lane; v < E * NV * Nfp; v += 64) {
+        // w_0 = L_0 s, one row per (face, position) item, position fastest
+        for (int v = lane; v < E * FB * Nfp; v += TPE) {
           const int gg = v % Nfp;
           const int rest = v / Nfp;
-          const int vec = rest % NV;
-          const int el = rest / NV;
-          const T* sv = sfl[w][el][vec];
+          const int fl = rest % FB;
+          const int el = rest / FB;
+          const Pair<T>* sv = sfl[w][el][fl];
           const uint2 pp = *reinterpret_cast<const uint2*>(t_l0p[gg]);
-          T acc = t_l0c[0][gg] * sv[gg];
-          acc += t_l0c[1][gg] * sv[(pp.x >> 8) & 255];
-          acc += t_l0c[2][gg] * sv[(pp.x >> 16) & 255];
-          acc += t_l0c[3][gg] * sv[pp.x >> 24];
-          acc += t_l0c[4][gg] * sv[pp.y & 255];
-          acc += t_l0c[5][gg] * sv[(pp.y >> 8) & 255];
-          acc += t_l0c[6][gg] * sv[(pp.y >> 16) & 255];
-          slev[w][el][vec][gg] = acc;
+          const int pos[7] = {gg, (int)((pp.x >> 8) & 255), (int)((pp.x >> 16) & 255), (int)(pp.x >> 24),
+                              (int)(pp.y & 255), (int)((pp.y >> 8) & 255), (int)((pp.y >> 16) & 255)};
+          T ap = 0, au = 0;
+#pragma unroll
+          for (int q = 0; q < 7; ++q) {
+            const T c = t_l0c[q][gg];
+            const Pair<T> x = sv[pos[q]];
+            ap += c * x.p;
+            au += c * x.u;
+          }
+          slev[w][el][fl][gg] = Pair<T>{ap, au};
         }
-        wave_lds_sync();
+        team_sync<TW>();
 
-        // one-degree reductions, level j = 1..N, one row per (vector, position) item
+        // one-degree reductions, level j = 1..N, one row per (face, position) item
 #pragma unroll
         for (int j = 1; j <= N; ++j) {
           const int out0 = level_off(j, N);
           const int Tm = tri_of(N - j);
-          for (int v = lane; v < E * NV * Tm; v += 64) {
+          for (int v = lane; v < E * FB * Tm; v += TPE) {
             const int s = v % Tm;
             const int rest = v / Tm;
-            const int vec = rest % NV;
-            const int el = rest / NV;
+            const int fl = rest % FB;
+            const int el = rest / FB;
             const int nn = out0 + s;
-            T* wv = slev[w][el][vec];
+            Pair<T>* wv = slev[w][el][fl];
             const uint32_t ip = t_lvp[nn];
             const int i0 = ip & 0xffff, i2 = ip >> 16;
-            wv[nn] = t_lvc[0][nn] * wv[i0] + t_lvc[1][nn] * wv[i0 + 1] + t_lvc[2][nn] * wv[i2];
+            const T c0 = t_lvc[0][nn], c1 = t_lvc[1][nn], c2 = t_lvc[2][nn];
+            const Pair<T> x0 = wv[i0], x1 = wv[i0 + 1], x2 = wv[i2];
+            wv[nn] = Pair<T>{c0 * x0.p + c1 * x1.p + c2 * x2.p, c0 * x0.u + c1 * x1.u + c2 * x2.u};
           }
-          wave_lds_sync();
+          team_sync<TW>();
         }
 
         // gather the lifted values of this batch into the nodes
 #pragma unroll
         for (int r = 0; r < NPL; ++r) {
-          const int v = lane + 64 * r;
+          const int v = lane + TPE * r;
           if (v >= E * Np) continue;
           const int el = v / Np;
           const int n = v - el * Np;
@@ -532,15 +582,16 @@ void bb_stage_kernel(StageArgs<T> A) {
             const int af = (ap >> (8 * f)) & 255;
             const int pos = t_proj[n][f];
             const T ell = t_ell[af];
-            const T lp = ell * slev[w][el][fl][pos];
-            const T lu = ell * slev[w][el][FB + fl][pos];
+            const Pair<T> x = slev[w][el][fl][pos];
+            const T lp = ell * x.p;
+            const T lu = ell * x.u;
             rhs[r][0] += lp;
             rhs[r][1] += fr[0] * lu;
             rhs[r][2] += fr[1] * lu;
             rhs[r][3] += fr[2] * lu;
           }
         }
-        if (FB < 4) wave_lds_sync();
+        if (FB < 4) team_sync<TW>();
       }
     }
 
@@ -549,7 +600,7 @@ void bb_stage_kernel(StageArgs<T> A) {
       const int32_t se = A.src_elem ? A.src_elem[shot] : -1;
 #pragma unroll
       for (int r = 0; r < NPL; ++r) {
-        const int v = lane + 64 * r;
+        const int v = lane + TPE * r;
         const int el = v / Np;
         if (v < E * Np && e0 + el == se) rhs[r][0] += amp * A.src_coef[shot * Np + (v - el * Np)];
       }
@@ -558,7 +609,7 @@ void bb_stage_kernel(StageArgs<T> A) {
     // ---- update / store -------------------------------------------------------------
 #pragma unroll
     for (int r = 0; r < NPL; ++r) {
-      const int v = lane + 64 * r;
+      const int v = lane + TPE * r;
       const int el = v / Np;
       if (v >= E * Np || e0 + el >= K) continue;
       const uint32_t off = noff[r];
@@ -569,7 +620,8 @@ void bb_stage_kernel(StageArgs<T> A) {
         for (int f = 0; f < 4; ++f) {
           const T rs = dt * rhs[r][f] + rk_a * rv[r][f];
           st(res_s + f * KNp, off, rs);
-          st(qout_s + f * KNp, off, qv[r][f] + rk_b * rs);
+          const T qo = S::LATE_RES ? sq[w][el][f / PK][v - el * Np][f % PK] : qv[r][f];
+          st(qout_s + f * KNp, off, qo + rk_b * rs);
         }
       } else {
 #pragma unroll
