@@ -64,6 +64,8 @@ struct Shape {
   static constexpr int E = (Np <= 32) ? (64 / Np) : 1;    // elements per group
   // waves that share one element group in the single-stage kernel (the whole
   // workgroup when > 1); batched launches always use one wave per group
+  // (measured: teams pay off only where one wave per group needs more than
+  // half the register file, N >= 8 in FP64)
   static constexpr int TW = sizeof(T) == 8 ? (N >= 8 ? 4 : 1) : 1;
   // faces per lift batch (bounds the LDS of the face vectors), for one-wave
   // teams and for workgroup teams
@@ -656,7 +658,7 @@ void bb_stage_kernel(StageArgs<T> A) {
 }
 
 template <int N, typename T, int MODE, int WPB>
-static hipError_t resident_grid(int64_t groups, int64_t* grid_out) {
+static hipError_t resident_grid(int64_t groups, int per_wg, int64_t* grid_out) {
   static int resident = 0;  // co-resident workgroups per CU for this instantiation
   static int cus = 0;
   if (resident == 0) {
@@ -669,7 +671,7 @@ static hipError_t resident_grid(int64_t groups, int64_t* grid_out) {
     if (occ < 1) return hipErrorInvalidConfiguration;
     resident = occ;
   }
-  const int64_t needed = (groups + WPB - 1) / WPB;
+  const int64_t needed = (groups + per_wg - 1) / per_wg;  // workgroups with work
   int64_t grid = (int64_t)resident * cus;
   if (grid > ((needed + 7) / 8) * 8) grid = ((needed + 7) / 8) * 8;
   if (MODE == kBatched) grid = grid / 8 * 8;  // stay within the co-resident bound
@@ -684,11 +686,12 @@ static hipError_t launch_one(const StageArgs<T>& a, hipStream_t stream) {
   using S = Shape<N, T>;
   const int64_t groups = (a.K + S::E - 1) / S::E;
   if (groups <= 0) return hipSuccess;
+  constexpr int WPB = S::TW > 1 ? S::TW : 4;
   int64_t grid = 0;
-  const hipError_t e = resident_grid<N, T, MODE, 4>(groups, &grid);
+  const hipError_t e = resident_grid<N, T, MODE, WPB>(groups, WPB / S::TW, &grid);
   if (e != hipSuccess) return e;
   (void)hipGetLastError();  // drop errors left by earlier, unrelated calls
-  hipLaunchKernelGGL((bb_stage_kernel<N, T, MODE, 4>), dim3((unsigned)grid), dim3(256), 0, stream, a);
+  hipLaunchKernelGGL((bb_stage_kernel<N, T, MODE, WPB>), dim3((unsigned)grid), dim3(64 * WPB), 0, stream, a);
   return hipGetLastError();
 }
 
@@ -698,7 +701,7 @@ static hipError_t launch_batched_one(const StageArgs<T>& a, hipStream_t stream) 
   const int64_t groups = (a.K + S::E - 1) / S::E * a.shots;
   if (groups <= 0 || a.nstages <= 0) return hipSuccess;
   int64_t grid = 0;
-  const hipError_t e = resident_grid<N, T, kBatched, WPB>(groups, &grid);
+  const hipError_t e = resident_grid<N, T, kBatched, WPB>(groups, WPB, &grid);
   if (e != hipSuccess) return e;
   StageArgs<T> args = a;
   void* params[] = {&args};
