@@ -77,6 +77,6 @@ constexpr NodalDims nodal_dims(int N) {
   return d;
 }
 
-enum StageMode { kStage = 0, kRhsFull = 1, kRhsVolume = 2, kRhsSurface = 3, kBatched = 4 };
+enum StageMode { kStage = 0, kRhsFull = 1, kRhsVolume = 2, kRhsSurface = 3, kBatched = 4, kBatchedRecord = 5 };
 
 }  // namespace bbdg

@@ -108,11 +108,15 @@ __device__ __forceinline__ void team_sync() {
 }
 
 // Occupancy target (waves per SIMD) that bounds the register allocation.
-template <int N, typename T, int TW>
+template <int N, typename T, int TW, bool BATCH>
 struct Occ {
   static constexpr int f64[10] = {0, 2, 3, 4, 4, 4, 3, 3, 2, 2};
   static constexpr int f32[10] = {0, 3, 4, 5, 5, 5, 4, 4, 3, 3};
-  static constexpr int value = TW > 1 ? 4 : (sizeof(T) == 8 ? f64[N] : f32[N]);
+  // the batched kernel carries more stage state (buffers, coefficients, source)
+  static constexpr int f64b[10] = {0, 2, 3, 4, 4, 4, 3, 3, 2, 2};
+  static constexpr int f32b[10] = {0, 3, 4, 5, 5, 5, 4, 4, 3, 3};
+  static constexpr int value =
+      TW > 1 ? 4 : (sizeof(T) == 8 ? (BATCH ? f64b[N] : f64[N]) : (BATCH ? f32b[N] : f32[N]));
 };
 
 template <int N>
@@ -184,17 +188,18 @@ __device__ __forceinline__ double ricker(double t, double f0, double tshift) {
 }
 
 template <int N, typename T, int MODE, int WPB>
-__global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(Occ<N, T, (MODE == kBatched ? 1 : Shape<N, T>::TW)>::value)))
+__global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(Occ<N, T, (MODE >= kBatched ? 1 : Shape<N, T>::TW), MODE >= kBatched>::value)))
 void bb_stage_kernel(StageArgs<T> A) {
   using S = Shape<N, T>;
-  constexpr bool kBatch = (MODE == kBatched);
+  constexpr bool kBatch = (MODE == kBatched || MODE == kBatchedRecord);
+  constexpr bool kRecord = (MODE == kBatchedRecord);  // stage record for the adjoint
   constexpr int TW = kBatch ? 1 : S::TW;  // waves per element team
   static_assert(WPB % TW == 0 && (TW == 1 || TW == WPB), "a team is one wave or the whole workgroup");
   using M = Team<N, T, TW>;
   constexpr int TEAMS = WPB / TW, TPE = M::TPE;
   constexpr int Np = S::Np, Nfp = S::Nfp, E = S::E, NPL = M::NPL, NFI = M::NFI;
   constexpr int FB = TW > 1 ? S::FBT : S::FB1, GEO = S::GEO;
-  constexpr bool kUpdate = (MODE == kStage || MODE == kBatched);
+  constexpr bool kUpdate = (MODE == kStage || kBatch);
   constexpr int PK = sizeof(T) == 4 ? 4 : 1;
   constexpr bool kVol = (MODE != kRhsSurface);
   constexpr bool kSurf = (MODE != kRhsVolume);
@@ -516,7 +521,7 @@ void bb_stage_kernel(StageArgs<T> A) {
             }
             sp = fr[3] * jp - fr[4] * jgu;
             su = fr[5] * jgu - (T)0.5 * jp;
-            if (kBatch && A.rec_j) {
+            if constexpr (kRecord) {
               T* rj = A.rec_j + ((stage * A.shots + shot) * K + e0 + el) * (8 * Nfp) + f * (2 * Nfp) + gg;
               rj[0] = jp;
               rj[Nfp] = jgu;
@@ -616,7 +621,7 @@ void bb_stage_kernel(StageArgs<T> A) {
       if (v >= E * Np || e0 + el >= K) continue;
       const uint32_t off = noff[r];
       if constexpr (kUpdate) {
-        if (kBatch && A.rec_p) A.rec_p[(stage * A.shots + shot) * KNp + off] = rhs[r][0];
+        if constexpr (kRecord) A.rec_p[(stage * A.shots + shot) * KNp + off] = rhs[r][0];
         const T dt = kBatch ? (T)A.dtd : A.dt;
 #pragma unroll
         for (int f = 0; f < 4; ++f) {
@@ -674,9 +679,9 @@ static hipError_t resident_grid(int64_t groups, int per_wg, int64_t* grid_out) {
   const int64_t needed = (groups + per_wg - 1) / per_wg;  // workgroups with work
   int64_t grid = (int64_t)resident * cus;
   if (grid > ((needed + 7) / 8) * 8) grid = ((needed + 7) / 8) * 8;
-  if (MODE == kBatched) grid = grid / 8 * 8;  // stay within the co-resident bound
+  if (MODE >= kBatched) grid = grid / 8 * 8;  // stay within the co-resident bound
   else grid = ((grid + 7) / 8) * 8;
-  if (grid < 8) return MODE == kBatched ? hipErrorCooperativeLaunchTooLarge : (*grid_out = 8, hipSuccess);
+  if (grid < 8) return MODE >= kBatched ? hipErrorCooperativeLaunchTooLarge : (*grid_out = 8, hipSuccess);
   *grid_out = grid;
   return hipSuccess;
 }
@@ -695,18 +700,27 @@ static hipError_t launch_one(const StageArgs<T>& a, hipStream_t stream) {
   return hipGetLastError();
 }
 
-template <int N, typename T, int WPB>
-static hipError_t launch_batched_one(const StageArgs<T>& a, hipStream_t stream) {
+template <int N, typename T, int WPB, int MODE>
+static hipError_t launch_batched_mode(const StageArgs<T>& a, hipStream_t stream) {
   using S = Shape<N, T>;
   const int64_t groups = (a.K + S::E - 1) / S::E * a.shots;
   if (groups <= 0 || a.nstages <= 0) return hipSuccess;
   int64_t grid = 0;
-  const hipError_t e = resident_grid<N, T, kBatched, WPB>(groups, WPB, &grid);
+  const hipError_t e = resident_grid<N, T, MODE, WPB>(groups, WPB, &grid);
   if (e != hipSuccess) return e;
   StageArgs<T> args = a;
   void* params[] = {&args};
-  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(bb_stage_kernel<N, T, kBatched, WPB>),
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(bb_stage_kernel<N, T, MODE, WPB>),
                                     dim3((unsigned)grid), dim3(64 * WPB), params, 0, stream);
+}
+
+template <int N, typename T, int WPB>
+static hipError_t launch_batched_one(const StageArgs<T>& a, hipStream_t stream) {
+  if (a.rec_p || a.rec_j) {
+    if (!a.rec_p || !a.rec_j) return hipErrorInvalidValue;
+    return launch_batched_mode<N, T, WPB, kBatchedRecord>(a, stream);
+  }
+  return launch_batched_mode<N, T, WPB, kBatched>(a, stream);
 }
 
 template <typename T>
