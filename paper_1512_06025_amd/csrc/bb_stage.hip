@@ -81,13 +81,26 @@ struct Shape {
   static constexpr bool LATE_RES = sizeof(T) == 8 ? (N >= 6) : (N >= 8);
 };
 
+// Items (element, face, position < cnt) of the lift loops are laid out with a
+// position stride of the next power of two when that costs no extra pass over
+// the team's threads, so that decoding an item needs shifts, not divisions.
+__host__ __device__ constexpr int pow2ceil(int x) {
+  int p = 1;
+  while (p < x) p *= 2;
+  return p;
+}
+__host__ __device__ constexpr int item_stride(int cnt, int groups, int tpe) {
+  return (groups * pow2ceil(cnt) + tpe - 1) / tpe == (groups * cnt + tpe - 1) / tpe ? pow2ceil(cnt) : cnt;
+}
+
 // Per-thread counts for a team of TW waves (TPE threads) working on one group.
 template <int N, typename T, int TW>
 struct Team {
   using S = Shape<N, T>;
   static constexpr int TPE = 64 * TW;
   static constexpr int NPL = (S::E * S::Np + TPE - 1) / TPE;      // nodes per thread
-  static constexpr int NFI = (S::E * 4 * S::Nfp + TPE - 1) / TPE;  // face items per thread
+  static constexpr int SF = item_stride(S::Nfp, S::E * 4, TPE);   // face-item position stride
+  static constexpr int NFI = (S::E * 4 * SF + TPE - 1) / TPE;      // face items per thread
   static constexpr int NHG = (S::HG + TPE - 1) / TPE;
   static constexpr int NHE = (S::E * 4 + TPE - 1) / TPE;
 };
@@ -110,8 +123,8 @@ __device__ __forceinline__ void team_sync() {
 // Occupancy target (waves per SIMD) that bounds the register allocation.
 template <int N, typename T, int TW, bool BATCH>
 struct Occ {
-  static constexpr int f64[10] = {0, 2, 3, 4, 4, 4, 3, 3, 2, 2};
-  static constexpr int f32[10] = {0, 3, 4, 5, 5, 5, 4, 4, 3, 3};
+  static constexpr int f64[10] = {0, 2, 3, 4, 4, 4, 4, 3, 2, 2};
+  static constexpr int f32[10] = {0, 3, 4, 5, 5, 5, 5, 4, 4, 3};
   // the batched kernel carries more stage state (buffers, coefficients, source)
   static constexpr int f64b[10] = {0, 2, 3, 4, 4, 4, 3, 3, 2, 2};
   static constexpr int f32b[10] = {0, 3, 4, 5, 5, 5, 4, 4, 3, 3};
@@ -340,7 +353,7 @@ void bb_stage_kernel(StageArgs<T> A) {
 #pragma unroll
     for (int r = 0; r < NPL; ++r) {
       const int v = lane + TPE * r;
-      const int el = v / Np;
+      const int el = E == 1 ? 0 : v / Np;
       const int n = v - el * Np;
       const bool ok = (v < E * Np) && (e0 + el < K);
       noff[r] = ok ? (uint32_t)((e0 + el) * Np + n) : 0u;
@@ -358,13 +371,12 @@ void bb_stage_kernel(StageArgs<T> A) {
     if constexpr (kSurf) {
 #pragma unroll
       for (int r = 0; r < NFI; ++r) {
-        const int v = lane + TPE * r;
-        const int el = v / (4 * Nfp);
-        const int rem = v - el * 4 * Nfp;
-        const int f = rem / Nfp;
-        const int gg = rem - f * Nfp;
+        const unsigned v = lane + TPE * r;
+        const unsigned gg = v % M::SF;
+        const unsigned f = (v / M::SF) % 4;
+        const unsigned el = v / (4 * M::SF);
         uint32_t off = 0;
-        if (v < E * 4 * Nfp && e0 + el < K) {
+        if (el < (unsigned)E && gg < (unsigned)Nfp && e0 + el < K) {
           const int nb = she[w][el * 4 + f];
           const int info = shf[w][el * 4 + f];
           if (nb >= 0) off = (uint32_t)nb * Np + t_nbr[((info & 3) * 6 + (info >> 2)) * Nfp + gg];
@@ -411,7 +423,7 @@ void bb_stage_kernel(StageArgs<T> A) {
     for (int r = 0; r < NPL; ++r) {
       const int v = lane + TPE * r;
       if (v < E * Np) {
-        const int el = v / Np;
+        const int el = E == 1 ? 0 : v / Np;
         const int n = v - el * Np;
 #pragma unroll
         for (int f = 0; f < 4; ++f) sq[w][el][f / PK][n][f % PK] = qv[r][f];
@@ -431,7 +443,7 @@ void bb_stage_kernel(StageArgs<T> A) {
       for (int r = 0; r < NPL; ++r) {
         const int v = lane + TPE * r;
         if (v >= E * Np) continue;
-        const int el = v / Np;
+        const int el = E == 1 ? 0 : v / Np;
         const int n = v - el * Np;
         const uint32_t ap = t_alpha[n];
         const T av[4] = {(T)(ap & 255), (T)((ap >> 8) & 255), (T)((ap >> 16) & 255), (T)(ap >> 24)};
@@ -495,12 +507,11 @@ void bb_stage_kernel(StageArgs<T> A) {
         // flux on the face nodes of faces fb0 .. fb0+FB-1
 #pragma unroll
         for (int r = 0; r < NFI; ++r) {
-          const int v = lane + TPE * r;
-          const int el = v / (4 * Nfp);
-          const int rem = v - el * 4 * Nfp;
-          const int f = rem / Nfp;
-          const int gg = rem - f * Nfp;
-          if (v >= E * 4 * Nfp || f < fb0 || f >= fb0 + FB) continue;
+          const unsigned v = lane + TPE * r;
+          const unsigned gg = v % M::SF;
+          const int f = (v / M::SF) % 4;
+          const unsigned el = v / (4 * M::SF);
+          if (el >= (unsigned)E || gg >= (unsigned)Nfp || f < fb0 || f >= fb0 + FB) continue;
           T sp = 0, su = 0;
           if (e0 + el < K) {
             const int n = t_fnode[f * Nfp + gg];
@@ -532,15 +543,15 @@ void bb_stage_kernel(StageArgs<T> A) {
         team_sync<TW>();
 
         // w_0 = L_0 s, one row per (face, position) item, position fastest
-        for (int v = lane; v < E * FB * Nfp; v += TPE) {
-          const int gg = v % Nfp;
-          const int rest = v / Nfp;
-          const int fl = rest % FB;
-          const int el = rest / FB;
-          const Pair<T>* sv = sfl[w][el][fl];
+        constexpr unsigned SL0 = item_stride(Nfp, E * FB, TPE);
+        for (unsigned v = lane; v < E * FB * SL0; v += TPE) {
+          const unsigned gg = v % SL0;
+          const unsigned rest = v / SL0;  // = el * FB + face in the batch
+          if (gg >= Nfp) continue;
+          const Pair<T>* sv = &sfl[w][0][0][0] + rest * Nfp;
           const uint2 pp = *reinterpret_cast<const uint2*>(t_l0p[gg]);
-          const int pos[7] = {gg, (int)((pp.x >> 8) & 255), (int)((pp.x >> 16) & 255), (int)(pp.x >> 24),
-                              (int)(pp.y & 255), (int)((pp.y >> 8) & 255), (int)((pp.y >> 16) & 255)};
+          const unsigned pos[7] = {gg, (pp.x >> 8) & 255, (pp.x >> 16) & 255, pp.x >> 24,
+                                   pp.y & 255, (pp.y >> 8) & 255, (pp.y >> 16) & 255};
           T ap = 0, au = 0;
 #pragma unroll
           for (int q = 0; q < 7; ++q) {
@@ -549,7 +560,7 @@ void bb_stage_kernel(StageArgs<T> A) {
             ap += c * x.p;
             au += c * x.u;
           }
-          slev[w][el][fl][gg] = Pair<T>{ap, au};
+          (&slev[w][0][0][0])[rest * Np + gg] = Pair<T>{ap, au};
         }
         team_sync<TW>();
 
@@ -558,15 +569,15 @@ void bb_stage_kernel(StageArgs<T> A) {
         for (int j = 1; j <= N; ++j) {
           const int out0 = level_off(j, N);
           const int Tm = tri_of(N - j);
-          for (int v = lane; v < E * FB * Tm; v += TPE) {
-            const int s = v % Tm;
-            const int rest = v / Tm;
-            const int fl = rest % FB;
-            const int el = rest / FB;
-            const int nn = out0 + s;
-            Pair<T>* wv = slev[w][el][fl];
+          const unsigned SM = item_stride(Tm, E * FB, TPE);
+          for (unsigned v = lane; v < E * FB * SM; v += TPE) {
+            const unsigned s = v % SM;
+            const unsigned rest = v / SM;  // = el * FB + face in the batch
+            if (s >= (unsigned)Tm) continue;
+            const unsigned nn = out0 + s;
+            Pair<T>* wv = &slev[w][0][0][0] + rest * Np;
             const uint32_t ip = t_lvp[nn];
-            const int i0 = ip & 0xffff, i2 = ip >> 16;
+            const unsigned i0 = ip & 0xffff, i2 = ip >> 16;
             const T c0 = t_lvc[0][nn], c1 = t_lvc[1][nn], c2 = t_lvc[2][nn];
             const Pair<T> x0 = wv[i0], x1 = wv[i0 + 1], x2 = wv[i2];
             wv[nn] = Pair<T>{c0 * x0.p + c1 * x1.p + c2 * x2.p, c0 * x0.u + c1 * x1.u + c2 * x2.u};
@@ -579,7 +590,7 @@ void bb_stage_kernel(StageArgs<T> A) {
         for (int r = 0; r < NPL; ++r) {
           const int v = lane + TPE * r;
           if (v >= E * Np) continue;
-          const int el = v / Np;
+          const int el = E == 1 ? 0 : v / Np;
           const int n = v - el * Np;
           const uint32_t ap = t_alpha[n];
 #pragma unroll
@@ -608,7 +619,7 @@ void bb_stage_kernel(StageArgs<T> A) {
 #pragma unroll
       for (int r = 0; r < NPL; ++r) {
         const int v = lane + TPE * r;
-        const int el = v / Np;
+        const int el = E == 1 ? 0 : v / Np;
         if (v < E * Np && e0 + el == se) rhs[r][0] += amp * A.src_coef[shot * Np + (v - el * Np)];
       }
     }
@@ -617,7 +628,7 @@ void bb_stage_kernel(StageArgs<T> A) {
 #pragma unroll
     for (int r = 0; r < NPL; ++r) {
       const int v = lane + TPE * r;
-      const int el = v / Np;
+      const int el = E == 1 ? 0 : v / Np;
       if (v >= E * Np || e0 + el >= K) continue;
       const uint32_t off = noff[r];
       if constexpr (kUpdate) {
