@@ -48,11 +48,38 @@ struct AShape {
   static constexpr int NPL = (E * Np + 63) / 64;
   static constexpr int NFI = (E * 4 * Nfp + 63) / 64;
   static constexpr int FB = sizeof(T) == 8 ? (N >= 8 ? 1 : (N >= 6 ? 2 : 4)) : (N >= 8 ? 2 : 4);
-  static constexpr int NV = 2 * FB;
+
   static constexpr int WPB = (N >= 8) ? 2 : 4;
+  static constexpr int HG = E * kGeoStride;  // header doubles per group
+  static constexpr int NHG = (HG + 63) / 64;
+  static constexpr int NHE = (E * 4 + 63) / 64;
   // per element geometry (T): grad lambda_0..3 (12), kappa; per face f at
   // 16 + 8 f: g (3), a_p, a_u, b_u, |g|, d(tau terms) packed below
   static constexpr int GEO = 48;
+};
+
+template <typename T>
+struct alignas(2 * sizeof(T)) APair {
+  T p, u;
+};
+
+// position stride of the lift items: the next power of two when that costs
+// no extra pass over the 64 lanes (decoding then needs shifts only)
+__host__ __device__ constexpr int a_pow2ceil(int x) {
+  int p = 1;
+  while (p < x) p *= 2;
+  return p;
+}
+__host__ __device__ constexpr int a_item_stride(int cnt, int groups) {
+  return (groups * a_pow2ceil(cnt) + 63) / 64 == (groups * cnt + 63) / 64 ? a_pow2ceil(cnt) : cnt;
+}
+
+// occupancy target (waves per SIMD) bounding the register allocation
+template <int N, typename T>
+struct AOcc {
+  static constexpr int f64[10] = {0, 2, 3, 3, 4, 4, 3, 3, 2, 2};
+  static constexpr int f32[10] = {0, 3, 3, 4, 5, 5, 4, 4, 3, 3};
+  static constexpr int value = sizeof(T) == 8 ? f64[N] : f32[N];
 };
 
 template <int N>
@@ -65,13 +92,43 @@ struct AEll {
   static constexpr double value(int j) { return ((j & 1) ? -1.0 : 1.0) * binom(N, j) / (1.0 + j); }
 };
 
+// One group's header (per-element geometry, connectivity) held across the
+// previous group's work: lane v keeps header word v.
+template <int N, typename T>
+struct AHeader {
+  double geo[AShape<N, T>::NHG];
+  int32_t etoe[AShape<N, T>::NHE];
+  uint32_t fo[AShape<N, T>::NHE];
+};
+
+template <int N, typename T>
+__device__ __forceinline__ void load_aheader(AHeader<N, T>& h, const AdjointArgs<T>& A, int64_t e0, int lane) {
+  using S = AShape<N, T>;
+#pragma unroll
+  for (int r = 0; r < S::NHG; ++r) {
+    const int v = lane + 64 * r;
+    int64_t idx = e0 * kGeoStride + v;
+    if (v >= S::HG || idx >= A.K * kGeoStride) idx = 0;
+    h.geo[r] = A.geo[idx];
+  }
+#pragma unroll
+  for (int r = 0; r < S::NHE; ++r) {
+    const int v = lane + 64 * r;
+    int64_t idx = e0 * 4 + v;
+    if (v >= S::E * 4 || idx >= A.K * 4) idx = 0;
+    h.etoe[r] = A.etoe[idx];
+    h.fo[r] = A.etofo[idx];
+  }
+}
+
 }  // namespace
 
 template <int N, typename T>
-__global__ __launch_bounds__((64 * AShape<N, T>::WPB)) void bb_adjoint_kernel(AdjointArgs<T> A) {
+__global__ __launch_bounds__((64 * AShape<N, T>::WPB)) __attribute__((amdgpu_waves_per_eu(AOcc<N, T>::value)))
+void bb_adjoint_kernel(AdjointArgs<T> A) {
   using S = AShape<N, T>;
   constexpr int Np = S::Np, Nfp = S::Nfp, E = S::E, NPL = S::NPL, NFI = S::NFI;
-  constexpr int FB = S::FB, NV = S::NV, WPB = S::WPB, GEO = S::GEO;
+  constexpr int FB = S::FB, WPB = S::WPB, GEO = S::GEO;
   constexpr TabLayout L = tab_layout(N);
 
   __shared__ uint16_t t_fnode[4 * Nfp];
@@ -89,11 +146,12 @@ __global__ __launch_bounds__((64 * AShape<N, T>::WPB)) void bb_adjoint_kernel(Ad
 
   __shared__ T su[WPB][E][4][Np];       // u = rb + b_s qb
   __shared__ T sh[WPB][E][4][Np];       // h_i = grad(lambda_i) . u_vel
-  __shared__ T slev[WPB][E][NV][Np];    // layered face vectors
-  __shared__ T sfl[WPB][E][NV][Nfp];    // L^{fT} results on the face nodes
-  __shared__ T sface[WPB][E][4][2][Nfp];  // per-face node contributions
+  __shared__ APair<T> slev[WPB][E][FB][Np];  // layered face vectors (p, velocity) pairs
+  __shared__ APair<T> sfl[WPB][E][FB][Nfp];  // L^{fT} results on the face nodes
+  __shared__ T sface[WPB][E][4][3][Nfp];  // per-face node contributions (p, u, tau term)
   __shared__ double sred[WPB][E][5];    // gradient partial sums
   __shared__ T sgeo[WPB][E][GEO];
+  __shared__ double shg[WPB][E * kGeoStride];
   __shared__ int32_t she[WPB][E * 4];
   __shared__ uint8_t shf[WPB][E * 4];
 
@@ -162,14 +220,92 @@ __global__ __launch_bounds__((64 * AShape<N, T>::WPB)) void bb_adjoint_kernel(Ad
   const int64_t wstride = (int64_t)(gridDim.x >> 3) * WPB;
   const T a_s = A.a_s, b_s = A.b_s, dt = A.dt;
 
-  for (int64_t g = g_lo + (int64_t)(blockIdx.x >> 3) * WPB + w; g < g_hi; g += wstride) {
+  int64_t g = g_lo + (int64_t)(blockIdx.x >> 3) * WPB + w;
+  AHeader<N, T> hd;
+  if (g < g_hi) load_aheader<N, T>(hd, A, (int64_t)((uint32_t)g % (uint32_t)G) * E, lane);
+
+  for (; g < g_hi; g += wstride) {
     const int64_t shot = (int64_t)((uint32_t)g / (uint32_t)G);
     const int64_t e0 = (g - shot * G) * E;
     const int64_t sb = shot * 4 * KNp;
     const int64_t zb = shot * K * 8 * Nfp;
 
-    // ---- geometry and connectivity ----------------------------------------------
+    // ---- header of this group -> LDS; prefetch the next one -----------------------
     wave_sync();
+#pragma unroll
+    for (int r = 0; r < S::NHG; ++r) {
+      const int v = lane + 64 * r;
+      if (v < S::HG) shg[w][v] = hd.geo[r];
+    }
+#pragma unroll
+    for (int r = 0; r < S::NHE; ++r) {
+      const int v = lane + 64 * r;
+      if (v < E * 4) {
+        she[w][v] = e0 + v / 4 < K ? hd.etoe[r] : -1;
+        shf[w][v] = (uint8_t)hd.fo[r];
+      }
+    }
+    wave_sync();
+    if (g + wstride < g_hi)
+      load_aheader<N, T>(hd, A, (int64_t)((uint32_t)(g + wstride) % (uint32_t)G) * E, lane);
+
+    // ---- issue every load of this group together --------------------------------
+    // own adjoint state and recorded pressure right-hand side
+    T qv[NPL][4], uv[NPL][4], pv[NPL];
+    uint32_t noff[NPL];
+#pragma unroll
+    for (int r = 0; r < NPL; ++r) {
+      const int v = lane + 64 * r;
+      const int el = E == 1 ? 0 : v / Np;
+      const int n = v - el * Np;
+      const bool ok = (v < E * Np) && (e0 + el < K);
+      noff[r] = ok ? (uint32_t)((e0 + el) * Np + n) : 0u;
+#pragma unroll
+      for (int f = 0; f < 4; ++f) {
+        qv[r][f] = ok ? A.qb[sb + f * KNp + noff[r]] : (T)0;
+        uv[r][f] = ok ? A.rb[sb + f * KNp + noff[r]] : (T)0;
+      }
+      pv[r] = ok ? A.rec_p[shot * KNp + noff[r]] : (T)0;
+    }
+    // per face item: the neighbour's face adjoint (pull) and the recorded jumps
+    T zq[NFI][2], rjv[NFI][2];
+#pragma unroll
+    for (int r = 0; r < NFI; ++r) {
+      const int v = lane + 64 * r;
+      zq[r][0] = zq[r][1] = rjv[r][0] = rjv[r][1] = 0;
+      if (v >= E * 4 * Nfp) continue;
+      const int el = v / (4 * Nfp);
+      const int rem = v - el * 4 * Nfp;
+      const int f = rem / Nfp;
+      const int gg = rem - f * Nfp;
+      const int64_t k = e0 + el;
+      if (k >= K) continue;
+      const T* rj = A.rec_j + (shot * K + k) * 8 * Nfp + f * 2 * Nfp + gg;
+      rjv[r][0] = rj[0];
+      rjv[r][1] = rj[Nfp];
+      const int nb = she[w][el * 4 + f];
+      if (A.pull && nb >= 0) {
+        const int info = shf[w][el * 4 + f];
+        const int g2 = t_fperm[(info >> 2) * Nfp + gg];
+        const T* zs = A.z_in + zb + ((int64_t)nb * 4 + (info & 3)) * 2 * Nfp + g2;
+        zq[r][0] = zs[0];
+        zq[r][1] = zs[Nfp];
+      }
+    }
+    // gradient sums of this group (read-modify-write at the end)
+    constexpr int NG = (E * 5 + 63) / 64;
+    double gold[NG];
+#pragma unroll
+    for (int r = 0; r < NG; ++r) {
+      const int v = lane + 64 * r;
+      gold[r] = 0.0;
+      if (v < E * 5 && e0 + v / 5 < K) {
+        const int el = v / 5, c = v - 5 * el;
+        gold[r] = c == 0 ? A.gk[shot * K + e0 + el] : A.gt[(shot * K + e0 + el) * 4 + c - 1];
+      }
+    }
+
+    // ---- geometry --------------------------------------------------------------------
     for (int v = lane; v < E * 4; v += 64) {
       const int el = v >> 2, f = v & 3;
       const int64_t k = e0 + el;
@@ -178,11 +314,9 @@ __global__ __launch_bounds__((64 * AShape<N, T>::WPB)) void bb_adjoint_kernel(Ad
         for (int c = 0; c < 3; ++c) o[3 * f + c] = 0;
         if (f == 0) o[12] = 1;
         for (int c = 0; c < 8; ++c) o[16 + 8 * f + c] = 1;
-        she[w][v] = -1;
-        shf[w][v] = 0;
         continue;
       }
-      const double* ge = A.geo + k * kGeoStride;
+      const double* ge = shg[w] + el * kGeoStride;
       double gx, gy, gz;
       if (f == 0) {
         gx = -(ge[0] + ge[3] + ge[6]);
@@ -207,28 +341,9 @@ __global__ __launch_bounds__((64 * AShape<N, T>::WPB)) void bb_adjoint_kernel(Ad
       fr[5] = (T)ge[14 + f];     // b_u = s / (4 |g|)
       fr[6] = (T)F;
       fr[7] = (T)0;
-      she[w][v] = A.etoe[k * 4 + f];
-      shf[w][v] = A.etofo[k * 4 + f];
     }
     wave_sync();
 
-    // ---- own values --------------------------------------------------------------
-    T qv[NPL][4], uv[NPL][4], pv[NPL];
-    uint32_t noff[NPL];
-#pragma unroll
-    for (int r = 0; r < NPL; ++r) {
-      const int v = lane + 64 * r;
-      const int el = v / Np;
-      const int n = v - el * Np;
-      const bool ok = (v < E * Np) && (e0 + el < K);
-      noff[r] = ok ? (uint32_t)((e0 + el) * Np + n) : 0u;
-#pragma unroll
-      for (int f = 0; f < 4; ++f) {
-        qv[r][f] = ok ? A.qb[sb + f * KNp + noff[r]] : (T)0;
-        uv[r][f] = ok ? A.rb[sb + f * KNp + noff[r]] : (T)0;
-      }
-      pv[r] = ok ? A.rec_p[shot * KNp + noff[r]] : (T)0;
-    }
 
     // ---- neighbour terms of the previous reverse stage -----------------------------
     if (A.pull) {
@@ -240,19 +355,10 @@ __global__ __launch_bounds__((64 * AShape<N, T>::WPB)) void bb_adjoint_kernel(Ad
         const int rem = v - el * 4 * Nfp;
         const int f = rem / Nfp;
         const int gg = rem - f * Nfp;
-        T zp = 0, zu = 0;
-        const int nb = she[w][el * 4 + f];
-        if (nb >= 0) {
-          const int info = shf[w][el * 4 + f];
-          const int g2 = t_fperm[(info >> 2) * Nfp + gg];
-          const T* zs = A.z_in + zb + ((int64_t)nb * 4 + (info & 3)) * 2 * Nfp + g2;
-          zp = zs[0];
-          zu = zs[Nfp];
-        }
         // the neighbour's g is -(|g_nb|/|g_f|) g_f and zu carries |g_nb|:
         // the velocity adjoint gains -(g_f/|g_f|) zu
-        sface[w][el][f][0][gg] = zp;
-        sface[w][el][f][1][gg] = -zu / sgeo[w][el][16 + 8 * f + 6];
+        sface[w][el][f][0][gg] = zq[r][0];
+        sface[w][el][f][1][gg] = -zq[r][1] / sgeo[w][el][16 + 8 * f + 6];
       }
       wave_sync();
 #pragma unroll
@@ -351,8 +457,7 @@ __global__ __launch_bounds__((64 * AShape<N, T>::WPB)) void bb_adjoint_kernel(Ad
           const T* fr = sgeo[w][el] + 16 + 8 * f;
           const T ell = t_ell[(ap >> (8 * f)) & 255];
           const int pos = t_proj[n][f];
-          slev[w][el][fl][pos] = ell * uv[r][0];
-          slev[w][el][FB + fl][pos] = ell * (fr[0] * uv[r][1] + fr[1] * uv[r][2] + fr[2] * uv[r][3]);
+          slev[w][el][fl][pos] = APair<T>{ell * uv[r][0], ell * (fr[0] * uv[r][1] + fr[1] * uv[r][2] + fr[2] * uv[r][3])};
         }
       }
       wave_sync();
@@ -360,29 +465,36 @@ __global__ __launch_bounds__((64 * AShape<N, T>::WPB)) void bb_adjoint_kernel(Ad
       for (int j = N - 1; j >= 0; --j) {
         const int out0 = level_off(j, N);
         const int Tm = tri_of(N - j);
-        for (int v = lane; v < E * NV * Tm; v += 64) {
-          const int s = v % Tm;
-          const int rest = v / Tm;
-          const int vec = rest % NV;
-          const int el = rest / NV;
-          const int nn = out0 + s;
-          T* wv = slev[w][el][vec];
-          wv[nn] += t_rsc[0][nn] * wv[t_rsp[nn][0]] + t_rsc[1][nn] * wv[t_rsp[nn][1]] +
-                    t_rsc[2][nn] * wv[t_rsp[nn][2]];
+        const unsigned SM = a_item_stride(Tm, E * FB);
+        for (unsigned v = lane; v < E * FB * SM; v += 64) {
+          const unsigned s = v % SM;
+          const unsigned rest = v / SM;  // = el * FB + face in the batch
+          if (s >= (unsigned)Tm) continue;
+          const unsigned nn = out0 + s;
+          APair<T>* wv = &slev[w][0][0][0] + rest * Np;
+          const T c0 = t_rsc[0][nn], c1 = t_rsc[1][nn], c2 = t_rsc[2][nn];
+          const APair<T> x0 = wv[t_rsp[nn][0]], x1 = wv[t_rsp[nn][1]], x2 = wv[t_rsp[nn][2]];
+          const APair<T> y = wv[nn];
+          wv[nn] = APair<T>{y.p + c0 * x0.p + c1 * x1.p + c2 * x2.p, y.u + c0 * x0.u + c1 * x1.u + c2 * x2.u};
         }
         wave_sync();
       }
       // z = L_0 y_0 (L_0 symmetric)
-      for (int v = lane; v < E * NV * Nfp; v += 64) {
-        const int gg = v % Nfp;
-        const int rest = v / Nfp;
-        const int vec = rest % NV;
-        const int el = rest / NV;
-        const T* sv = slev[w][el][vec];
-        T z = 0;
+      constexpr unsigned SL0 = a_item_stride(Nfp, E * FB);
+      for (unsigned v = lane; v < E * FB * SL0; v += 64) {
+        const unsigned gg = v % SL0;
+        const unsigned rest = v / SL0;
+        if (gg >= (unsigned)Nfp) continue;
+        const APair<T>* sv = &slev[w][0][0][0] + rest * Np;
+        T zp = 0, zu = 0;
 #pragma unroll
-        for (int q = 0; q < 7; ++q) z += t_l0c[q][gg] * sv[t_l0p[gg][q]];
-        sfl[w][el][vec][gg] = z;
+        for (int q = 0; q < 7; ++q) {
+          const T c = t_l0c[q][gg];
+          const APair<T> x = sv[t_l0p[gg][q]];
+          zp += c * x.p;
+          zu += c * x.u;
+        }
+        (&sfl[w][0][0][0])[rest * Nfp + gg] = APair<T>{zp, zu};
       }
       wave_sync();
       // transposed flux on the face nodes of this batch
@@ -399,7 +511,8 @@ __global__ __launch_bounds__((64 * AShape<N, T>::WPB)) void bb_adjoint_kernel(Ad
         T dp = 0, du = 0, tau = 0;
         if (k < K) {
           const T* fr = sgeo[w][el] + 16 + 8 * f;
-          const T zp = sfl[w][el][f - fb0][gg], zu = sfl[w][el][FB + f - fb0][gg];
+          const APair<T> zz = sfl[w][el][f - fb0][gg];
+          const T zp = zz.p, zu = zz.u;
           // sp = a_p [[p]] - a_u g.[[u]],  su = b_u g.[[u]] - [[p]]/2
           const T jbp = fr[3] * zp - (T)0.5 * zu;
           const T jbg = fr[5] * zu - fr[4] * zp;
@@ -416,19 +529,18 @@ __global__ __launch_bounds__((64 * AShape<N, T>::WPB)) void bb_adjoint_kernel(Ad
             dp = (T)(-2) * jbp;
           }
           // d/ds of the flux at fixed jumps: -a_p/s [[p]] and g.[[u]]/(4|g|), s = 4 |g| b_u
-          const T* rj = A.rec_j + (shot * K + k) * 8 * Nfp + f * 2 * Nfp + gg;
           const T s = (T)4 * fr[6] * fr[5];
-          tau = zp * (-fr[3] / s) * rj[0] + zu * rj[Nfp] / ((T)4 * fr[6]);
+          tau = zp * (-fr[3] / s) * rjv[r][0] + zu * rjv[r][1] / ((T)4 * fr[6]);
         }
         sface[w][el][f][0][gg] = dp;
         sface[w][el][f][1][gg] = du;
-        sfl[w][el][f - fb0][gg] = tau;  // z no longer needed: reuse for the tau term
+        sface[w][el][f][2][gg] = tau;
       }
       wave_sync();
       for (int v = lane; v < E * FB; v += 64) {
         const int el = v / FB, fl = v - el * FB;
         double t = 0.0;
-        for (int gg = 0; gg < Nfp; ++gg) t += (double)sfl[w][el][fl][gg];
+        for (int gg = 0; gg < Nfp; ++gg) t += (double)sface[w][el][fb0 + fl][2][gg];
         sred[w][el][1 + fb0 + fl] = t;
       }
       wave_sync();
@@ -471,14 +583,16 @@ __global__ __launch_bounds__((64 * AShape<N, T>::WPB)) void bb_adjoint_kernel(Ad
       sred[w][el][0] = t;
     }
     wave_sync();
-    for (int v = lane; v < E * 5; v += 64) {
-      const int el = v / 5, c = v - el * 5;
+#pragma unroll
+    for (int r = 0; r < NG; ++r) {
+      const int v = lane + 64 * r;
+      if (v >= E * 5 || e0 + v / 5 >= K) continue;
+      const int el = v / 5, c = v - 5 * el;
       const int64_t k = e0 + el;
-      if (k >= K) continue;
       if (c == 0) {
-        A.gk[shot * K + k] += (double)dt * sred[w][el][0] / (double)sgeo[w][el][12];
+        A.gk[shot * K + k] = gold[r] + (double)dt * sred[w][el][0] / (double)sgeo[w][el][12];
       } else {
-        A.gt[(shot * K + k) * 4 + c - 1] += (double)dt * sred[w][el][c];
+        A.gt[(shot * K + k) * 4 + c - 1] = gold[r] + (double)dt * sred[w][el][c];
       }
     }
 
