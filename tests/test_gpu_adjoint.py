@@ -44,7 +44,7 @@ def _oracle(VX, EToV, m, src, rec, obs, N, bc="rigid", dt=2e-3, t0=0.08):
 
 
 @pytest.mark.parametrize("N,ckpt,bc", [(1, 0, "rigid"), (2, 0, "rigid"), (3, 4, "rigid"), (4, 1, "rigid"),
-                                       (3, 0, "pressure_release"), (6, 3, "rigid")])
+                                       (5, 2, "rigid"), (3, 0, "pressure_release"), (6, 3, "rigid")])
 def test_gradient_matches_oracle_fp64(N, ckpt, bc):
     import paper_1512_06025_amd as P
     VX, EToV, m, src, rec, obs = _case(N)
