@@ -74,7 +74,7 @@ def time_gpu(P, torch, N, mesh, c, q0, dt, steps, warmup, dtype, basis="bb"):
     ms = e0.elapsed_time(e1)
     finite = bool(torch.isfinite(q).all().item())
     s.close()
-    return ms, finite
+    return ms, finite, q
 
 
 def time_batched(P, torch, workload, steps):
@@ -103,12 +103,18 @@ def time_batched(P, torch, workload, steps):
     gbs = algorithmic_bytes_per_element(N, 4) * K * S / (stage_us * 1e-6) / 1e9
     finite = bool(torch.isfinite(q).all().item() and torch.isfinite(tr).all().item())
     bs.close()
+    # the same run in FP64 (untimed) for the FP32 error of the traces
+    b64 = P.BatchedSolver(N, mesh, c, S, sources=workload.source_positions(S), receivers=workload.receiver_grid(),
+                          f0=cfg["f0"], ts=cfg["ts"], dtype="f64", wpb=4)
+    tr64 = b64.run(b64.empty_state(), dt, steps)
+    err32 = float(torch.linalg.norm(tr.double() - tr64) / torch.linalg.norm(tr64))
+    b64.close()
     return {"workload": "%d shots, Ricker f0=%g, %d receivers, unit cube %d^3x6 = %d tets, N=%d, c~U[%g,%g], "
                         "FP32, %d steps in one persistent launch" % (S, cfg["f0"], 64, cfg["n"], K, N,
                                                                      cfg["c"][0], cfg["c"][1], steps),
             "value": 4.0 * K * Np * S * stages / (ms * 1e-3), "unit": "DoF-stage/s", "ms_total": ms,
             "stage_us": stage_us, "achieved_GBs": gbs, "frac": gbs / HBM_PEAK_GBS, "waves_per_workgroup": wpb,
-            "finite": finite}
+            "finite": finite, "traces_rel_l2_error_vs_fp64": err32}
 
 
 def time_gradient(P, torch, workload, steps):
@@ -140,12 +146,21 @@ def time_gradient(P, torch, workload, steps):
     torch.cuda.synchronize()
     t_fwd, t_adj = ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2])
     finite = bool(torch.isfinite(g).all().item())
+    g = g.clone()
+    mf.close()
+    # the same gradient with FP64 states (untimed) for the FP32 error
+    m64 = P.Misfit(N, mesh, np.ones(K), S, src, rec, d_obs, dt, steps, f0=cfg["f0"], ts=cfg["ts"],
+                   ckpt_every=cfg["ckpt_every"], dtype="f64")
+    J64 = float(m64.evaluate().item())
+    g64 = m64.gradient()
+    m64.close()
     out = {"workload": "misfit gradient dJ/dm, %d shots (Ricker f0=%g on z=0.9), 64 receivers, %d^3x6 = %d tets, "
                        "N=%d, FP32 states / FP64 sums, %d steps, checkpoints every %d" % (
                            S, cfg["f0"], cfg["n"], K, N, steps, cfg["ckpt_every"]),
            "J": float(J.item()), "forward_ms": t_fwd, "reverse_ms": t_adj,
-           "grad_over_forward": (t_fwd + t_adj) / t_fwd, "finite": finite}
-    mf.close()
+           "grad_over_forward": (t_fwd + t_adj) / t_fwd, "reverse_over_forward": t_adj / t_fwd,
+           "finite": finite, "J_rel_error_vs_fp64": abs(float(J.item()) - J64) / abs(J64),
+           "grad_rel_l2_error_vs_fp64": float(torch.linalg.norm(g - g64) / torch.linalg.norm(g64))}
     return out
 
 
@@ -236,7 +251,7 @@ def main():
 
     stages = 5 * args.steps
     dof = 4.0 * K * Np
-    ms64, ok64 = time_gpu(P, torch, N, mesh, c, q0, dt, args.steps, args.warmup, "f64")
+    ms64, ok64, q64 = time_gpu(P, torch, N, mesh, c, q0, dt, args.steps, args.warmup, "f64")
     value = dof * stages / (ms64 * 1e-3)
     stage_us = ms64 * 1e3 / stages
     bytes_launch = algorithmic_bytes_per_element(N, 8) * K
@@ -278,18 +293,21 @@ def main():
         },
     }
     if not args.no_fp32:
-        ms32, ok32 = time_gpu(P, torch, N, mesh, c, q0, dt, args.steps, args.warmup, "f32")
+        ms32, ok32, q32 = time_gpu(P, torch, N, mesh, c, q0, dt, args.steps, args.warmup, "f32")
         st32 = ms32 * 1e3 / stages
         a32 = algorithmic_bytes_per_element(N, 4) * K / (st32 * 1e-6) / 1e9
+        # both runs did warm-up + steps steps from q0; the FP64 path matches the oracle to 1e-12
+        err32 = float(torch.linalg.norm(q32.double() - q64) / torch.linalg.norm(q64))
         out["fp32"] = {"value": dof * stages / (ms32 * 1e-3), "ms_per_step": ms32 / args.steps,
-                       "stage_us": st32, "achieved_GBs": a32, "frac": a32 / HBM_PEAK_GBS, "finite": ok32}
+                       "stage_us": st32, "achieved_GBs": a32, "frac": a32 / HBM_PEAK_GBS, "finite": ok32,
+                       "rel_l2_error_vs_fp64": err32}
     if not args.no_nodal:
         x0 = ic.initial_state(N, VX, EToV, workload.INITIAL_FIELDS[cfg["ic"]], basis="nodal")
         nod = {}
         for dt_name, bb_ms in (("f64", ms64), ("f32", out.get("fp32", {}).get("ms_per_step", 0) * args.steps)):
             if dt_name == "f32" and args.no_fp32:
                 continue
-            msn, okn = time_gpu(P, torch, N, mesh, c, x0, dt, args.steps, args.warmup, dt_name, basis="nodal")
+            msn, okn, _ = time_gpu(P, torch, N, mesh, c, x0, dt, args.steps, args.warmup, dt_name, basis="nodal")
             flop = K * (24 * Np * Np + 32 * Np * Nfp)  # dense volume + lift per stage
             nod[dt_name] = {"value": dof * stages / (msn * 1e-3), "stage_us": msn * 1e3 / stages,
                             "tflops": flop * stages / (msn * 1e-3) / 1e12, "finite": okn,
