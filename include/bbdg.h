@@ -217,7 +217,7 @@ size_t bbdg_batched_work_bytes(const bbdg_solver* s, int64_t shots);
  *   traces:   device (steps, shots, R) of the element type: the pressure at
  *             every receiver after every step.  May be NULL when R = 0.
  *   work:     device, >= bbdg_batched_work_bytes(s, shots), 256-byte aligned.
- *   wpb:      wavefronts per workgroup, 2 or 4; 0 = the value
+ *   wpb:      wavefronts per workgroup, 2, 4 or 8; 0 = the value
  *             bbdg_tune_batched chose for this shot count (4 if not tuned).
  * shots * ceil(K / E) must stay below 2^32 (E = elements per wavefront).
  * Fails with BBDG_E_RESIDENT, before anything runs, if the grid cannot be
@@ -228,7 +228,7 @@ int bbdg_run_batched(bbdg_solver* s, void* q, int64_t shots, const int32_t* src_
                      int64_t steps, int wpb, void* stream);
 
 /* Autotuner of the batched launch shape: times two-step batched runs of
- * `shots` zero states for every wavefronts-per-workgroup candidate (2, 4),
+ * `shots` zero states for every wavefronts-per-workgroup candidate (2, 4, 8),
  * stores the fastest in the handle (used by bbdg_run_batched with wpb = 0)
  * and returns it in *wpb.  scratch: device, >= bbdg_batched_work_bytes(s,
  * shots) + shots * 4 * K * Np elements, 256-byte aligned; its contents are

@@ -744,6 +744,7 @@ hipError_t launch_batched(int N, int wpb, const StageArgs<T>& a, hipStream_t str
   case NN:                                                        \
     if (wpb == 2) return launch_batched_one<NN, T, 2>(a, stream); \
     if (wpb == 4) return launch_batched_one<NN, T, 4>(a, stream); \
+    if (wpb == 8) return launch_batched_one<NN, T, 8>(a, stream); \
     return hipErrorInvalidValue;
   switch (N) {
     BBDG_BATCH_CASE(1)

@@ -1050,7 +1050,7 @@ int bbdg_run_batched(bbdg_solver* s, void* q, int64_t shots, const int32_t* src_
   if (!batched_shape_ok(s, shots)) return BBDG_E_ARG;
   if (src_elem && !src_coef) return BBDG_E_ARG;
   if (R > 0 && (!rec_elem || !rec_coef || !traces)) return BBDG_E_ARG;
-  if (wpb != 0 && wpb != 2 && wpb != 4) return BBDG_E_ARG;
+  if (wpb != 0 && wpb != 2 && wpb != 4 && wpb != 8) return BBDG_E_ARG;
   if (!std::isfinite(t0) || !std::isfinite(dt) || !std::isfinite(f0) || !std::isfinite(ts)) return BBDG_E_NONFINITE;
   if (src_elem && !(f0 > 0.0)) return BBDG_E_ARG;
   if (((uintptr_t)work) % 256 != 0) return BBDG_E_ARG;
@@ -1084,7 +1084,7 @@ int bbdg_tune_batched(bbdg_solver* s, int64_t shots, void* scratch, int* wpb, vo
     (void)hipEventDestroy(e0);
     return BBDG_E_DEVICE;
   }
-  const int cand[2] = {2, 4};
+  const int cand[3] = {2, 4, 8};
   int best = 0, rc = BBDG_OK;
   float best_ms = 0.f;
   for (int c : cand) {

@@ -73,7 +73,7 @@ def test_launch_shapes_agree_bitwise():
     """Waves per workgroup change only the work distribution, not the arithmetic."""
     P, mesh, c, prob, src, rec = _case(3, n=3, drop_last=0, shots=3)
     outs = []
-    for wpb in (2, 4):
+    for wpb in (2, 4, 8):
         bs = P.BatchedSolver(3, mesh, c, 3, sources=src, receivers=rec, dtype="f64", wpb=wpb)
         q = bs.empty_state()
         tr = bs.run(q, 1e-3, 4, t0=0.1)
@@ -86,7 +86,7 @@ def test_launch_shapes_agree_bitwise():
 def test_autotuner_picks_a_candidate():
     P, mesh, c, prob, src, rec = _case(4, n=3, drop_last=0, shots=2)
     bs = P.BatchedSolver(4, mesh, c, 2, sources=src, receivers=rec, dtype="f32")
-    assert bs.tune() in (2, 4)
+    assert bs.tune() in (2, 4, 8)
     q = bs.empty_state()
     tr = bs.run(q, 1e-3, 3, t0=0.1)
     assert torch.isfinite(tr).all() and torch.isfinite(q).all()
