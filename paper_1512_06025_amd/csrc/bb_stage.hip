@@ -73,9 +73,9 @@ struct Shape {
   static constexpr int FBT = 2;
   static constexpr int HG = E * kGeoStride;               // header doubles per group
   // per-element derived geometry (type T): grad lambda_0..3 (12), kappa, pad,
-  // then per face f at 16 + 8 f: g_x, g_y, g_z, a_p, a_u, b_u, pad, pad with
+  // then per face f at 16 + 6 f: g_x, g_y, g_z, a_p, a_u, b_u with
   //   sp = a_p [[p]] - a_u g.[[u]],  su = b_u g.[[u]] - [[p]]/2.
-  static constexpr int GEO = 48;
+  static constexpr int GEO = 40;
   // register-lean variant for high orders: the LSRK residual is loaded after
   // the volume term and the own coefficients are re-read from LDS at the update
   static constexpr bool LATE_RES = sizeof(T) == 8 ? (N >= 6) : (N >= 8);
@@ -123,7 +123,7 @@ __device__ __forceinline__ void team_sync() {
 // Occupancy target (waves per SIMD) that bounds the register allocation.
 template <int N, typename T, int TW, bool BATCH>
 struct Occ {
-  static constexpr int f64[10] = {0, 2, 3, 4, 4, 4, 4, 3, 2, 2};
+  static constexpr int f64[10] = {0, 2, 3, 4, 4, 4, 3, 3, 2, 2};
   static constexpr int f32[10] = {0, 3, 4, 5, 5, 5, 5, 4, 4, 3};
   // the batched kernel carries more stage state (buffers, coefficients, source)
   static constexpr int f64b[10] = {0, 2, 3, 4, 4, 4, 3, 3, 2, 2};
@@ -213,7 +213,11 @@ void bb_stage_kernel(StageArgs<T> A) {
   constexpr int Np = S::Np, Nfp = S::Nfp, E = S::E, NPL = M::NPL, NFI = M::NFI;
   constexpr int FB = TW > 1 ? S::FBT : S::FB1, GEO = S::GEO;
   constexpr bool kUpdate = (MODE == kStage || kBatch);
-  constexpr int PK = sizeof(T) == 4 ? 4 : 1;
+  // FP32 up to N = 6 keeps (h_i, p) pairs per node (one 8-byte read per
+  // direction, 40-byte node stride free of bank conflicts); otherwise the
+  // five values are stored field by field (less LDS)
+  constexpr bool kPairSq = sizeof(T) == 4 && N <= 6;
+  constexpr int SQW = kPairSq ? 10 : 5;  // words per node of sq
   constexpr bool kVol = (MODE != kRhsSurface);
   constexpr bool kSurf = (MODE != kRhsVolume);
   constexpr TabLayout L = tab_layout(N);
@@ -234,11 +238,15 @@ void bb_stage_kernel(StageArgs<T> A) {
   // per-wave buffers
   // the element's coefficients, field-major in double, (p,u,v,w) packed into
   // one 16-byte vector per node in float
-  __shared__ __attribute__((aligned(16))) T sq[TEAMS][E][4 / PK][Np][PK];
+  // per node: p and h_i = grad(lambda_i) . u (i = 0..3), see kPairSq
+  __shared__ __attribute__((aligned(16))) T sq[TEAMS][E][SQW][Np];
   __shared__ Pair<T> sfl[TEAMS][E][FB][Nfp];
   __shared__ Pair<T> slev[TEAMS][E][FB][Np];
   __shared__ __attribute__((aligned(16))) T sgeo[TEAMS][E][GEO];
-  __shared__ double shg[TEAMS][E * kGeoStride];
+  // the header staging area is dead once geometry and h_i are derived, so it
+  // shares memory with the lift layers when they are large enough
+  constexpr bool kAliasHg = sizeof(Pair<T>) * FB * Np >= sizeof(double) * kGeoStride;
+  __shared__ double shg_own[kAliasHg ? 1 : TEAMS][kAliasHg ? 1 : E * kGeoStride];
   __shared__ int32_t she[TEAMS][E * 4];
   __shared__ uint8_t shf[TEAMS][E * 4];
 
@@ -292,6 +300,28 @@ void bb_stage_kernel(StageArgs<T> A) {
 
   const int lane0 = tid % TPE;                              // thread within the team
   const int w = __builtin_amdgcn_readfirstlane(tid / TPE);  // team index (uniform)
+  // sq accessors: (p, h_i) of node n of element el, and the store of a node
+  double* const shg_w = kAliasHg ? reinterpret_cast<double*>(&slev[w][0][0][0]) : &shg_own[kAliasHg ? 0 : w][0];
+  auto sq_pair = [&](int el, int n, int i) -> Pair<T> {
+    if constexpr (kPairSq) {
+      // node layout: (h_0, p, h_1, p, h_2, p, h_3, p, pad, pad)
+      const float2 x = *reinterpret_cast<const float2*>(&sq[w][el][0][0] + SQW * n + 2 * i);
+      return Pair<T>{(T)x.y, (T)x.x};
+    } else {
+      return Pair<T>{sq[w][el][0][n], sq[w][el][1 + i][n]};
+    }
+  };
+  auto sq_put = [&](int el, int n, T pv, const T* hv) {
+    if constexpr (kPairSq) {
+      float2* o = reinterpret_cast<float2*>(&sq[w][el][0][0] + SQW * n);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) o[i] = make_float2(hv[i], pv);
+    } else {
+      sq[w][el][0][n] = pv;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) sq[w][el][1 + i][n] = hv[i];
+    }
+  };
   const int64_t K = A.K;
   const int64_t KNp = K * Np;
   const int64_t G = (K + E - 1) / E;  // element groups per shot
@@ -335,7 +365,7 @@ void bb_stage_kernel(StageArgs<T> A) {
 #pragma unroll
     for (int r = 0; r < M::NHG; ++r) {
       const int v = lane + TPE * r;
-      if (v < S::HG) shg[w][v] = hd.geo[r];
+      if (v < S::HG) shg_w[v] = hd.geo[r];
     }
 #pragma unroll
     for (int r = 0; r < M::NHE; ++r) {
@@ -393,7 +423,7 @@ void bb_stage_kernel(StageArgs<T> A) {
     for (int v = lane; v < E * 4; v += TPE) {
       const int el = v >> 2;
       const int f = v & 3;
-      const double* ge = shg[w] + el * kGeoStride;
+      const double* ge = shg_w + el * kGeoStride;
       double gx, gy, gz;  // grad lambda_f
       if (f == 0) {
         gx = -(ge[0] + ge[3] + ge[6]);
@@ -409,7 +439,7 @@ void bb_stage_kernel(StageArgs<T> A) {
       o[3 * f + 1] = (T)gy;
       o[3 * f + 2] = (T)gz;
       if (f == 0) o[12] = (T)ge[9];
-      T* fr = o + 16 + 8 * f;
+      T* fr = o + 16 + 6 * f;
       fr[0] = (T)(-2.0 * gx);
       fr[1] = (T)(-2.0 * gy);
       fr[2] = (T)(-2.0 * gz);
@@ -419,14 +449,22 @@ void bb_stage_kernel(StageArgs<T> A) {
     }
 
     // ---- own coefficients -> LDS -----------------------------------------------
+    T hreg[NPL][4];  // h_i of the own nodes
 #pragma unroll
     for (int r = 0; r < NPL; ++r) {
       const int v = lane + TPE * r;
       if (v < E * Np) {
         const int el = E == 1 ? 0 : v / Np;
         const int n = v - el * Np;
+        // h_i from grad(lambda_i) of the header (double, in LDS since the last sync)
+        const double* hg = shg_w + el * kGeoStride;
+        T* hv = hreg[r];
 #pragma unroll
-        for (int f = 0; f < 4; ++f) sq[w][el][f / PK][n][f % PK] = qv[r][f];
+        for (int i = 1; i < 4; ++i)
+          hv[i] = (T)hg[3 * i - 3] * qv[r][1] + (T)hg[3 * i - 2] * qv[r][2] + (T)hg[3 * i - 1] * qv[r][3];
+        hv[0] = (T)(-(hg[0] + hg[3] + hg[6])) * qv[r][1] + (T)(-(hg[1] + hg[4] + hg[7])) * qv[r][2] +
+                (T)(-(hg[2] + hg[5] + hg[8])) * qv[r][3];
+        sq_put(el, n, qv[r][0], hv);
       }
     }
     team_sync<TW>();
@@ -453,37 +491,25 @@ void bb_stage_kernel(StageArgs<T> A) {
         // neighbour alpha + e_a - e_b: pair index 3a + (b < a ? b : b - 1)
         auto P = [&](int ai, int bi) { return nb[3 * ai + (bi < ai ? bi : bi - 1)]; };
         const T* ge = sgeo[w][el];
-        T div = 0, gp[3] = {0, 0, 0};
-        // one pack of PK fields at a time: 13 x PK coefficients live
+        // grad p = sum_i grad(lambda_i) D^i p; div u = sum_i D^i h_i (D^i is
+        // linear and grad(lambda_i) is constant on the element)
+        T Dp[4], div = 0;
 #pragma unroll
-        for (int pk = 0; pk < 4 / PK; ++pk) {
-          T Di[PK][4];
+        for (int i = 0; i < 4; ++i) {
+          T dp = av[i] * qv[r][0], dh = av[i] * hreg[r][i];
 #pragma unroll
-          for (int i = 0; i < 4; ++i) {
-#pragma unroll
-            for (int c = 0; c < PK; ++c) Di[c][i] = av[i] * qv[r][pk * PK + c];
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
-              if (b == i) continue;
-              const T* x = sq[w][el][pk][P(i, b)];
-#pragma unroll
-              for (int c = 0; c < PK; ++c) Di[c][i] += av[b] * x[c];
-            }
+          for (int b = 0; b < 4; ++b) {
+            if (b == i) continue;
+            const Pair<T> x = sq_pair(el, P(i, b), i);
+            dp += av[b] * x.p;
+            dh += av[b] * x.u;
           }
-#pragma unroll
-          for (int c = 0; c < PK; ++c) {
-            const int f = pk * PK + c;
-            if (f == 0) {
-#pragma unroll
-              for (int d = 0; d < 3; ++d)
-                gp[d] = ge[d] * Di[c][0] + ge[3 + d] * Di[c][1] + ge[6 + d] * Di[c][2] + ge[9 + d] * Di[c][3];
-            } else {
-              div += ge[f - 1] * Di[c][0] + ge[3 + f - 1] * Di[c][1] + ge[6 + f - 1] * Di[c][2] +
-                     ge[9 + f - 1] * Di[c][3];
-            }
-          }
-          __builtin_amdgcn_sched_barrier(0);
+          Dp[i] = dp;
+          div += dh;
         }
+        T gp[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) gp[d] = ge[d] * Dp[0] + ge[3 + d] * Dp[1] + ge[6 + d] * Dp[2] + ge[9 + d] * Dp[3];
         rhs[r][0] = -ge[12] * div;
 #pragma unroll
         for (int d = 0; d < 3; ++d) rhs[r][1 + d] = -gp[d];
@@ -515,17 +541,18 @@ void bb_stage_kernel(StageArgs<T> A) {
           T sp = 0, su = 0;
           if (e0 + el < K) {
             const int n = t_fnode[f * Nfp + gg];
-            const T pm = sq[w][el][0][n][0], um = sq[w][el][1 / PK][n][1 % PK], vm = sq[w][el][2 / PK][n][2 % PK],
-                    wm = sq[w][el][3 / PK][n][3 % PK];
-            const T* fr = sgeo[w][el] + 16 + 8 * f;
+            // own trace: p and g_f . u = -2 h_f (g_f = -2 grad(lambda_f))
+            const Pair<T> own = sq_pair(el, n, f);
+            const T pm = own.p, gum = (T)(-2) * own.u;
+            const T* fr = sgeo[w][el] + 16 + 6 * f;
             const T gx = fr[0], gy = fr[1], gz = fr[2];
             T jp, jgu;
             if (she[w][el * 4 + f] >= 0) {
               jp = tr[r][0] - pm;
-              jgu = gx * (tr[r][1] - um) + gy * (tr[r][2] - vm) + gz * (tr[r][3] - wm);
+              jgu = gx * tr[r][1] + gy * tr[r][2] + gz * tr[r][3] - gum;
             } else if (A.bc == 0) {  // rigid wall mirror
               jp = 0;
-              jgu = (T)(-2) * (gx * um + gy * vm + gz * wm);
+              jgu = (T)(-2) * gum;
             } else {  // pressure-release mirror
               jp = (T)(-2) * pm;
               jgu = 0;
@@ -596,7 +623,7 @@ void bb_stage_kernel(StageArgs<T> A) {
 #pragma unroll
           for (int fl = 0; fl < FB; ++fl) {
             const int f = fb0 + fl;
-            const T* fr = sgeo[w][el] + 16 + 8 * f;
+            const T* fr = sgeo[w][el] + 16 + 6 * f;
             const int af = (ap >> (8 * f)) & 255;
             const int pos = t_proj[n][f];
             const T ell = t_ell[af];
@@ -638,8 +665,7 @@ void bb_stage_kernel(StageArgs<T> A) {
         for (int f = 0; f < 4; ++f) {
           const T rs = dt * rhs[r][f] + rk_a * rv[r][f];
           st(res_s + f * KNp, off, rs);
-          const T qo = S::LATE_RES ? sq[w][el][f / PK][v - el * Np][f % PK] : qv[r][f];
-          st(qout_s + f * KNp, off, qo + rk_b * rs);
+          st(qout_s + f * KNp, off, qv[r][f] + rk_b * rs);
         }
       } else {
 #pragma unroll
