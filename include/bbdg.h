@@ -75,6 +75,7 @@ extern "C" {
 #define BBDG_E_MODE (-9)      /* unknown right-hand-side mode */
 #define BBDG_E_OUTSIDE (-10)  /* a point lies in no element of the mesh */
 #define BBDG_E_RESIDENT (-11) /* a persistent grid that cannot be co-resident on the device */
+#define BBDG_E_TIMEOUT (-12)  /* a grid-wide barrier of a persistent launch timed out (see bbdg_status) */
 
 enum { BBDG_F64 = 0, BBDG_F32 = 1 };
 
@@ -197,12 +198,15 @@ int bbdg_source_coeffs(const bbdg_solver* s, int64_t n, const int32_t* elem, con
 
 /* Bytes of device work space that bbdg_run_batched needs for `shots` shots:
  * the LSRK residual and a second field buffer, 2 * shots * 4 * K * Np
- * elements. */
+ * elements, then the wavelet values at the stage times of one launch (5120
+ * doubles). */
 size_t bbdg_batched_work_bytes(const bbdg_solver* s, int64_t shots);
 
 /* Advances `shots` independent states on the solver's mesh and wavespeed by
- * `steps` LSRK4 steps of size dt from time t0, in ONE persistent cooperative
- * kernel launch (grid-wide barriers between the 5 * steps stages).
+ * `steps` LSRK4 steps of size dt from time t0, in persistent cooperative
+ * kernel launches of up to 1024 steps each (grid-wide barriers between the
+ * stages), each preceded by a small kernel that tabulates the wavelet at its
+ * stage times.
  *   q:        device (shots, 4, K, Np), in/out (shot-major; each shot is a
  *             (4, K, Np) field as above).
  *   src_elem: device int32 (shots): source element of each shot, or -1 for a
@@ -230,9 +234,12 @@ int bbdg_run_batched(bbdg_solver* s, void* q, int64_t shots, const int32_t* src_
 /* Autotuner of the batched launch shape: times two-step batched runs of
  * `shots` zero states for every wavefronts-per-workgroup candidate (2, 4, 8),
  * stores the fastest in the handle (used by bbdg_run_batched with wpb = 0)
- * and returns it in *wpb.  scratch: device, >= bbdg_batched_work_bytes(s,
+ * and returns it in *wpb.  A candidate whose grid barrier times out (see
+ * bbdg_status) or that cannot be co-resident is skipped.  Returns
+ * BBDG_E_TIMEOUT, without tuning, if an earlier run of the handle left a
+ * timeout unreported.  scratch: device, >= bbdg_batched_work_bytes(s,
  * shots) + shots * 4 * K * Np elements, 256-byte aligned; its contents are
- * overwritten.  Synchronises `stream`. */
+ * overwritten.  Synchronises the device. */
 int bbdg_tune_batched(bbdg_solver* s, int64_t shots, void* scratch, int* wpb, void* stream);
 
 /* ---- Receiver misfit and its gradient ---------------------------------------
@@ -286,6 +293,20 @@ int bbdg_copy_probe(const void* src, void* dst, size_t bytes, void* stream);
 
 /* Synchronises the solver's device and frees its tables.  Accepts NULL. */
 int bbdg_destroy(bbdg_solver* s);
+
+/* Status of the persistent (batched) launches of this handle: waits for the
+ * device to finish its work, then returns BBDG_E_TIMEOUT (and clears the
+ * flag) if a grid-wide barrier of any such launch since the last call timed
+ * out, else BBDG_OK.  Those barriers bound their wait (2 s unless
+ * bbdg_set_barrier_timeout says otherwise): a grid
+ * that the device does not keep co-resident ends every workgroup instead of
+ * hanging, and the run's outputs (q and traces of bbdg_run_batched, J and
+ * the gradient of the misfit calls) are filled with NaN. */
+int bbdg_status(bbdg_solver* s);
+
+/* Longest wait at a grid barrier of the handle's persistent launches, in
+ * seconds (0 .. 3600; default 2).  Fails with BBDG_E_ARG outside that range. */
+int bbdg_set_barrier_timeout(bbdg_solver* s, double seconds);
 
 /* The HIP error code (hipError_t) behind the last BBDG_E_LAUNCH or
  * BBDG_E_RESIDENT returned on this thread (0 if none): a diagnostic. */

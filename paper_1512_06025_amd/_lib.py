@@ -18,6 +18,7 @@ ERRORS = {
     0: "BBDG_OK", -1: "BBDG_E_ARG", -2: "BBDG_E_ORDER", -3: "BBDG_E_MESH",
     -4: "BBDG_E_NONFINITE", -5: "BBDG_E_DTYPE", -6: "BBDG_E_BC", -7: "BBDG_E_DEVICE",
     -8: "BBDG_E_LAUNCH", -9: "BBDG_E_MODE", -10: "BBDG_E_OUTSIDE", -11: "BBDG_E_RESIDENT",
+    -12: "BBDG_E_TIMEOUT",
 }
 
 # name -> (restype, argtypes)
@@ -50,6 +51,8 @@ SIGNATURES = {
                                     _c.c_double, _c.c_double, _c.c_int, _c.c_void_p, _c.c_void_p,
                                     _c.c_void_p, _c.c_void_p, _c.c_double, _c.c_double, _c.c_int64,
                                     _c.c_int, _c.c_void_p]),
+    "bbdg_status": (_c.c_int, [_c.c_void_p]),
+    "bbdg_set_barrier_timeout": (_c.c_int, [_c.c_void_p, _c.c_double]),
     "bbdg_tune_batched": (_c.c_int, [_c.c_void_p, _c.c_int64, _c.c_void_p, _c.POINTER(_c.c_int),
                                      _c.c_void_p]),
     "bbdg_set_wavespeed": (_c.c_int, [_c.c_void_p, _c.c_void_p]),

@@ -28,10 +28,10 @@ struct StageArgs {
   int64_t shots;
   T* qalt;
   int64_t nstages;
-  double t0, dtd;           // start time and step of the wavelet clock
+  double dtd;               // time step
   const int32_t* src_elem;  // S: source element of each shot (-1: none)
   const T* src_coef;        // S x Np: kappa (M^k)^{-1} B(lambda_s)
-  double f0, tshift;        // Ricker peak frequency and delay
+  const double* amp;        // nstages: wavelet value at each stage time
   int R;                    // receivers per shot
   const int32_t* rec_elem;  // R
   const T* rec_coef;        // R x Np: B_alpha(lambda_r)
@@ -41,15 +41,35 @@ struct StageArgs {
   // [[p]], g_f.[[u]] on the own face nodes, (stages, S, K, 4, 2, Nfp).
   T* rec_p;
   T* rec_j;
+  // Grid-barrier words of batched launches (kSyncBytes): arrival counters,
+  // zeroed before every launch, and a sticky timeout flag.
+  uint32_t* sync;
+  uint64_t barrier_timeout;  // longest wait at a grid barrier, wall-clock ticks
 };
+
+constexpr size_t kSyncBytes = 2048;
+constexpr int kSyncFlagWord = 288;  // index of the timeout flag in sync
 
 template <typename T>
 hipError_t launch_stage(int N, int mode, const StageArgs<T>& a, hipStream_t stream);
 
 // Persistent cooperative launch of a whole batched run; wpb = waves per
-// workgroup (1, 2 or 4).  Fails (no launch) when the grid cannot be co-resident.
+// workgroup (2, 4 or 8).  Fails (no launch) when the grid cannot be co-resident.
 template <typename T>
 hipError_t launch_batched(int N, int wpb, const StageArgs<T>& a, hipStream_t stream);
+
+// Zeroes the arrival counters of the grid barrier (one tiny kernel).
+hipError_t launch_barrier_reset(uint32_t* sync, hipStream_t stream);
+
+// Fills a[0..n) with NaN when the timeout flag of sync is set.
+template <typename T>
+hipError_t launch_poison(const uint32_t* sync, T* a, int64_t n, hipStream_t stream);
+
+// amp[i] = Ricker wavelet (peak frequency f0, delay ts) at the time of stage
+// i of the LSRK4 steps step0, step0 + 1, ... of a run from t0 with step dt:
+// t0 + (step0 + i / 5) dt + c_(i % 5) dt.
+hipError_t launch_wavelet(double* amp, int64_t nstages, double t0, int64_t step0, double dt, double f0, double ts,
+                          hipStream_t stream);
 
 // Arguments of the dense nodal comparator stage kernel: the same fields,
 // geometry and connectivity plus the dense operators

@@ -40,9 +40,10 @@
 //   LSRK4 update (fused): res = a res + dt rhs, q_out = q + b res.
 // Fields ping-pong between q_in and q_out, so no stage overwrites a trace
 // that another wave still reads.
-#include <hip/hip_cooperative_groups.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <algorithm>
 
 #include "bb_common.hpp"
 #include "bb_launch.hpp"
@@ -127,7 +128,7 @@ struct Occ {
   static constexpr int f32[10] = {0, 3, 4, 5, 5, 5, 5, 4, 4, 3};
   // the batched kernel carries more stage state (buffers, coefficients, source)
   static constexpr int f64b[10] = {0, 2, 3, 4, 4, 4, 3, 3, 2, 2};
-  static constexpr int f32b[10] = {0, 3, 4, 5, 5, 5, 4, 4, 3, 3};
+  static constexpr int f32b[10] = {0, 3, 4, 5, 5, 6, 4, 4, 3, 3};
   static constexpr int value =
       TW > 1 ? 4 : (sizeof(T) == 8 ? (BATCH ? f64b[N] : f64[N]) : (BATCH ? f32b[N] : f32[N]));
 };
@@ -194,19 +195,73 @@ __constant__ double kLsrkB[5] = {1432997174477.0 / 9575080441755.0, 516183667771
 __constant__ double kLsrkC[5] = {0.0, 1432997174477.0 / 9575080441755.0, 2526269341429.0 / 6820363962896.0,
                                  2006345519317.0 / 3224310063776.0, 2802321613138.0 / 2924317926251.0};
 
+// Grid-wide barrier of a persistent launch, with a bounded wait.
+// Workgroup b arrives on the counter of its group b % 8; the last arrival of
+// a group arrives on the top counter; the workgroups wait for the top counter
+// to reach 8 (stage + 1).  A wait longer than `timeout` ticks of the
+// constant-rate wall clock (a grid that is not co-resident) sets the sticky flag;
+// every workgroup that finds the flag set leaves the barrier with false and
+// ends, so the launch always drains.  One thread per workgroup releases
+// (agent scope) after the workgroup barrier and acquires before the second
+// one: fences are cumulative, so this covers the stores and loads of every
+// wave of the workgroup, and each workgroup writes back and invalidates the
+// XCD's L2 once per stage instead of once per wave.  Layout of sync (uint32 words, counters
+// on separate 128-byte lines): [32 g] group g, [256] top, [288] flag.
+constexpr int kSyncTop = 256, kSyncFlag = kSyncFlagWord;
+
+__device__ __forceinline__ bool grid_barrier(uint32_t* sync, int64_t stage, uint64_t timeout, int* s_ok) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    const uint32_t groups = gridDim.x >> 3;  // workgroups per arrival group (gridDim.x % 8 == 0)
+    const uint32_t round = (uint32_t)stage + 1;
+    uint32_t* mine = sync + 32 * (blockIdx.x & 7);
+    int ok = 1;
+    if (__hip_atomic_fetch_add(mine, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1 == groups * round) {
+      // the group's last arrival passes the group's releases on to the top counter
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+      __hip_atomic_fetch_add(sync + kSyncTop, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    const int64_t t0 = wall_clock64();
+    while (__hip_atomic_load(sync + kSyncTop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < 8 * round) {
+      if (__hip_atomic_load(sync + kSyncFlag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+        ok = 0;
+        break;
+      }
+      if ((uint64_t)(wall_clock64() - t0) > timeout) {
+        __hip_atomic_store(sync + kSyncFlag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ok = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    *s_ok = ok;
+  }
+  __syncthreads();
+  return *s_ok != 0;
+}
+
 // Ricker wavelet (1 - 2 pi^2 f0^2 s^2) exp(-pi^2 f0^2 s^2), s = t - tshift.
 __device__ __forceinline__ double ricker(double t, double f0, double tshift) {
   const double a = 3.14159265358979323846 * f0 * (t - tshift);
   return (1.0 - 2.0 * a * a) * exp(-a * a);
 }
 
+// Waves per element team: batched launches form teams only when the team is
+// the whole workgroup.
 template <int N, typename T, int MODE, int WPB>
-__global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(Occ<N, T, (MODE >= kBatched ? 1 : Shape<N, T>::TW), MODE >= kBatched>::value)))
+constexpr int team_waves() {
+  return (MODE >= kBatched && WPB != Shape<N, T>::TW) ? 1 : Shape<N, T>::TW;
+}
+
+template <int N, typename T, int MODE, int WPB>
+__global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(Occ<N, T, team_waves<N, T, MODE, WPB>(), MODE >= kBatched>::value)))
 void bb_stage_kernel(StageArgs<T> A) {
   using S = Shape<N, T>;
   constexpr bool kBatch = (MODE == kBatched || MODE == kBatchedRecord);
   constexpr bool kRecord = (MODE == kBatchedRecord);  // stage record for the adjoint
-  constexpr int TW = kBatch ? 1 : S::TW;  // waves per element team
+  constexpr int TW = team_waves<N, T, MODE, WPB>();  // waves per element team
   static_assert(WPB % TW == 0 && (TW == 1 || TW == WPB), "a team is one wave or the whole workgroup");
   using M = Team<N, T, TW>;
   constexpr int TEAMS = WPB / TW, TPE = M::TPE;
@@ -340,15 +395,18 @@ void bb_stage_kernel(StageArgs<T> A) {
   const T rk_a = kBatch ? (T)kLsrkA[s5] : A.rk_a;
   const T rk_b = kBatch ? (T)kLsrkB[s5] : A.rk_b;
   const int read_res = kBatch ? (s5 != 0) : A.read_res;
-  const T amp = kBatch ? (T)ricker(A.t0 + (double)(stage / 5) * A.dtd + kLsrkC[s5] * A.dtd, A.f0, A.tshift) : (T)0;
+  // the wavelet comes from a table: evaluating it here would keep its
+  // constants in registers through the whole stage loop
+  const T amp = (kBatch && A.src_elem) ? (T)A.amp[stage] : (T)0;
 
   int64_t g = g_lo + (int64_t)(blockIdx.x >> 3) * TEAMS + w;
   Header<N, T, TW> hd;
   // group g = shot * G + element group (shots * G < 2^32 is checked on the host)
-  if (g < g_hi) load_header<N, T, TW>(hd, A, kBatch ? (int64_t)((uint32_t)g % (uint32_t)G) : g, lane0);
+  if (g < g_hi) load_header<N, T, TW>(hd, A, kBatch ? (int64_t)__builtin_amdgcn_readfirstlane((uint32_t)g % (uint32_t)G) : g, lane0);
 
   for (; g < g_hi; g += wstride) {
-    const int64_t shot = kBatch ? (int64_t)((uint32_t)g / (uint32_t)G) : 0;
+    // (uniform per team: the division runs on the vector unit)
+    const int64_t shot = kBatch ? (int64_t)__builtin_amdgcn_readfirstlane((uint32_t)g / (uint32_t)G) : 0;
     const int64_t e0 = (g - shot * G) * E;
     const int64_t sb = shot * 4 * KNp;  // this shot's fields
     const T* qin_f[4] = {qin_b + sb, qin_b + sb + KNp, qin_b + sb + 2 * KNp, qin_b + sb + 3 * KNp};
@@ -417,7 +475,7 @@ void bb_stage_kernel(StageArgs<T> A) {
     }
     // ---- prefetch the next group's header -----------------------------------
     if (g + wstride < g_hi)
-      load_header<N, T, TW>(hd, A, kBatch ? (int64_t)((uint32_t)(g + wstride) % (uint32_t)G) : g + wstride, lane);
+      load_header<N, T, TW>(hd, A, kBatch ? (int64_t)__builtin_amdgcn_readfirstlane((uint32_t)(g + wstride) % (uint32_t)G) : g + wstride, lane);
 
     // ---- per-element derived geometry (one lane per element face) ------------
     for (int v = lane; v < E * 4; v += TPE) {
@@ -675,7 +733,8 @@ void bb_stage_kernel(StageArgs<T> A) {
   }  // element groups
 
   if constexpr (kBatch) {
-    cooperative_groups::this_grid().sync();
+    __shared__ int s_ok;
+    if (!grid_barrier(A.sync, stage, A.barrier_timeout, &s_ok)) return;
     // receivers read the pressure after the fifth stage of each step
     if (s5 == 4 && A.R > 0) {
       const int64_t items = A.shots * A.R;
@@ -698,6 +757,53 @@ void bb_stage_kernel(StageArgs<T> A) {
   }
   }  // stages
 }
+
+__global__ __launch_bounds__(256) void wavelet_kernel(double* amp, int64_t n, double t0, int64_t step0, double dt,
+                                                      double f0, double ts) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) amp[i] = ricker(t0 + (double)(step0 + i / 5) * dt + kLsrkC[i % 5] * dt, f0, ts);
+}
+
+hipError_t launch_wavelet(double* amp, int64_t nstages, double t0, int64_t step0, double dt, double f0, double ts,
+                          hipStream_t stream) {
+  if (nstages <= 0) return hipSuccess;
+  if (!amp) return hipErrorInvalidValue;
+  (void)hipGetLastError();
+  hipLaunchKernelGGL(wavelet_kernel, dim3((unsigned)((nstages + 255) / 256)), dim3(256), 0, stream, amp, nstages, t0,
+                     step0, dt, f0, ts);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(64) void barrier_reset_kernel(uint32_t* sync) {
+  // arrival counters and top counter; the sticky flag is kept
+  for (int i = threadIdx.x; i < kSyncFlag; i += 64) sync[i] = 0u;
+}
+
+hipError_t launch_barrier_reset(uint32_t* sync, hipStream_t stream) {
+  if (!sync) return hipErrorInvalidValue;
+  (void)hipGetLastError();
+  hipLaunchKernelGGL(barrier_reset_kernel, dim3(1), dim3(64), 0, stream, sync);
+  return hipGetLastError();
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void poison_kernel(const uint32_t* sync, T* a, int64_t n) {
+  if (sync[kSyncFlag] == 0u) return;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) a[i] = (T)NAN;
+}
+
+template <typename T>
+hipError_t launch_poison(const uint32_t* sync, T* a, int64_t n, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  if (!sync || !a) return hipErrorInvalidValue;
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 2048);
+  (void)hipGetLastError();
+  hipLaunchKernelGGL(poison_kernel<T>, dim3((unsigned)blocks), dim3(256), 0, stream, sync, a, n);
+  return hipGetLastError();
+}
+
+template hipError_t launch_poison<double>(const uint32_t*, double*, int64_t, hipStream_t);
+template hipError_t launch_poison<float>(const uint32_t*, float*, int64_t, hipStream_t);
 
 template <int N, typename T, int MODE, int WPB>
 static hipError_t resident_grid(int64_t groups, int per_wg, int64_t* grid_out) {
@@ -745,7 +851,7 @@ static hipError_t launch_batched_mode(const StageArgs<T>& a, hipStream_t stream)
   const int64_t groups = (a.K + S::E - 1) / S::E * a.shots;
   if (groups <= 0 || a.nstages <= 0) return hipSuccess;
   int64_t grid = 0;
-  const hipError_t e = resident_grid<N, T, MODE, WPB>(groups, WPB, &grid);
+  const hipError_t e = resident_grid<N, T, MODE, WPB>(groups, WPB / team_waves<N, T, MODE, WPB>(), &grid);
   if (e != hipSuccess) return e;
   StageArgs<T> args = a;
   void* params[] = {&args};

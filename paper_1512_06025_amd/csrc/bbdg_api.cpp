@@ -26,6 +26,8 @@ struct bbdg_solver {
   int32_t* d_etoe = nullptr;   // K x 4
   uint8_t* d_etofo = nullptr;  // K x 4
   uint16_t* d_tab = nullptr;   // tab_layout(N).size
+  uint32_t* d_sync = nullptr;  // grid-barrier counters and timeout flag of the persistent launches
+  double barrier_seconds = 2.0;  // longest wait at a grid barrier of those launches
   std::vector<double> h_J, h_kappa;  // host copies for the source vectors
   std::vector<double> h_geo;         // K x 10 as passed to create
   std::vector<int32_t> h_etoe;       // K x 4
@@ -371,6 +373,7 @@ void free_solver(bbdg_solver* s) {
   if (s->d_tab) (void)hipFree(s->d_tab);
   if (s->d_dr) (void)hipFree(s->d_dr);
   if (s->d_lift) (void)hipFree(s->d_lift);
+  if (s->d_sync) (void)hipFree(s->d_sync);
   delete s;
 }
 
@@ -460,10 +463,28 @@ void bernstein_values(int N, const double* lam, double* out) {
   }
 }
 
+// The barrier time limit in ticks of the device's wall clock.
+uint64_t barrier_ticks(const bbdg_solver* s) {
+  int khz = 0;
+  if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, s->device) != hipSuccess || khz <= 0)
+    khz = 100000;
+  return (uint64_t)(s->barrier_seconds * 1e3 * (double)khz);
+}
+
+// Steps per persistent launch of bbdg_run_batched: the wavelet table of one
+// launch (a double per stage) follows the two field buffers of the work space.
+constexpr int64_t kStepsPerLaunch = 1024;
+
+size_t batched_fields_bytes(const bbdg_solver* s, int64_t shots) {
+  return (2 * (size_t)shots * 4 * (size_t)s->K * np_of(s->N) * elem_size(s->dtype) + 255) / 256 * 256;
+}
+
+// One persistent launch of `steps` steps; amp holds the wavelet at each of
+// its 5 * steps stages (unused without sources).
 template <typename T>
-int run_batched_typed(bbdg_solver* s, T* q, int64_t shots, const int32_t* src_elem, const T* src_coef, double f0,
-                      double ts, int R, const int32_t* rec_elem, const T* rec_coef, T* traces, T* work, double t0,
-                      double dt, int64_t steps, int wpb, hipStream_t st) {
+int run_batched_launch(bbdg_solver* s, T* q, int64_t shots, const int32_t* src_elem, const T* src_coef,
+                       const double* amp, int R, const int32_t* rec_elem, const T* rec_coef, T* traces, T* work,
+                       double dt, int64_t steps, int wpb, hipStream_t st) {
   const int64_t n = 4 * s->K * (int64_t)np_of(s->N);
   StageArgs<T> a = base_args<T>(s);
   a.qin = q;
@@ -472,23 +493,49 @@ int run_batched_typed(bbdg_solver* s, T* q, int64_t shots, const int32_t* src_el
   a.qalt = work + shots * n;
   a.shots = shots;
   a.nstages = 5 * steps;
-  a.t0 = t0;
   a.dtd = dt;
   a.src_elem = src_elem;
   a.src_coef = src_coef;
-  a.f0 = f0;
-  a.tshift = ts;
+  a.amp = amp;
   a.R = R;
   a.rec_elem = rec_elem;
   a.rec_coef = rec_coef;
   a.traces = traces;
-  const hipError_t e = launch_batched<T>(s->N, wpb, a, st);
+  a.sync = s->d_sync;
+  a.barrier_timeout = barrier_ticks(s);
+  hipError_t e = launch_barrier_reset(s->d_sync, st);
+  if (e != hipSuccess) return hip_fail(e, BBDG_E_LAUNCH);
+  e = launch_batched<T>(s->N, wpb, a, st);
   if (e == hipErrorCooperativeLaunchTooLarge || e == hipErrorInvalidConfiguration) return hip_fail(e, BBDG_E_RESIDENT);
   if (e != hipSuccess) return hip_fail(e, BBDG_E_LAUNCH);
   // an odd stage count leaves the state in the second buffer
   if ((a.nstages & 1) &&
       hipMemcpyAsync(q, a.qalt, (size_t)(shots * n) * sizeof(T), hipMemcpyDeviceToDevice, st) != hipSuccess)
     return BBDG_E_DEVICE;
+  // a timed-out grid barrier leaves NaN in every output
+  e = launch_poison<T>(s->d_sync, q, shots * n, st);
+  if (e == hipSuccess && traces) e = launch_poison<T>(s->d_sync, traces, steps * shots * R, st);
+  if (e != hipSuccess) return hip_fail(e, BBDG_E_LAUNCH);
+  return BBDG_OK;
+}
+
+// A whole batched run: launches of at most kStepsPerLaunch steps, each
+// preceded by the evaluation of its wavelet table in the work space.
+template <typename T>
+int run_batched_typed(bbdg_solver* s, T* q, int64_t shots, const int32_t* src_elem, const T* src_coef, double f0,
+                      double ts, int R, const int32_t* rec_elem, const T* rec_coef, T* traces, T* work, double t0,
+                      double dt, int64_t steps, int wpb, hipStream_t st) {
+  double* amp = (double*)((char*)work + batched_fields_bytes(s, shots));
+  for (int64_t c0 = 0; c0 < steps; c0 += kStepsPerLaunch) {
+    const int64_t ns = std::min(kStepsPerLaunch, steps - c0);
+    if (src_elem) {
+      const hipError_t e = launch_wavelet(amp, 5 * ns, t0, c0, dt, f0, ts, st);
+      if (e != hipSuccess) return hip_fail(e, BBDG_E_LAUNCH);
+    }
+    const int rc = run_batched_launch<T>(s, q, shots, src_elem, src_coef, amp, R, rec_elem, rec_coef,
+                                         traces ? traces + c0 * shots * R : nullptr, work, dt, ns, wpb, st);
+    if (rc != BBDG_OK) return rc;
+  }
   return BBDG_OK;
 }
 
@@ -504,7 +551,8 @@ bool batched_shape_ok(const bbdg_solver* s, int64_t shots) {
 // part 256-byte aligned).
 struct GradLayout {
   int64_t C = 0, nseg = 0;
-  size_t state = 0, fwork = 0, ckpt = 0, traces = 0, rec_p = 0, rec_j = 0, rb = 0, qb = 0, z = 0, gk = 0, gt = 0;
+  size_t state = 0, fwork = 0, ckpt = 0, traces = 0, rec_p = 0, rec_j = 0, rb = 0, qb = 0, z = 0, gk = 0, gt = 0,
+         amp = 0;
   size_t total = 0;
 };
 
@@ -532,6 +580,7 @@ GradLayout grad_layout(const bbdg_solver* s, int64_t shots, int R, int64_t steps
   g.z = take(2 * S * K * 8 * Nfp * w);
   g.gk = take(S * K * sizeof(double));
   g.gt = take(S * K * 4 * sizeof(double));
+  g.amp = take(5 * (size_t)steps * sizeof(double));
   g.total = off;
   return g;
 }
@@ -552,6 +601,11 @@ int misfit_typed(bbdg_solver* s, int64_t shots, const T* q0, const int32_t* src_
   T* ckpt = (T*)(work + L.ckpt);
   T* traces = (T*)(work + L.traces);
   const int wpb = (s->tuned_shots == shots && s->tuned_wpb) ? s->tuned_wpb : 4;
+  double* amp = (double*)(work + L.amp);  // wavelet at every stage of the run
+  if (src_elem) {
+    const hipError_t e = launch_wavelet(amp, 5 * steps, t0, 0, dt, f0, ts, st);
+    if (e != hipSuccess) return hip_fail(e, BBDG_E_LAUNCH);
+  }
   if (forward) {
     if (q0) {
       if (hipMemcpyAsync(qs, q0, sbytes, hipMemcpyDeviceToDevice, st) != hipSuccess) return BBDG_E_DEVICE;
@@ -561,9 +615,8 @@ int misfit_typed(bbdg_solver* s, int64_t shots, const T* q0, const int32_t* src_
     for (int64_t seg = 0; seg < L.nseg; ++seg) {
       const int64_t ns = std::min(L.C, steps - seg * L.C);
       if (hipMemcpyAsync(ckpt + seg * n, qs, sbytes, hipMemcpyDeviceToDevice, st) != hipSuccess) return BBDG_E_DEVICE;
-      const int rc = run_batched_typed<T>(s, qs, shots, src_elem, src_coef, f0, ts, R, rec_elem, rec_coef,
-                                          traces + seg * L.C * shots * R, fwork, t0 + (double)(seg * L.C) * dt, dt,
-                                          ns, wpb, st);
+      const int rc = run_batched_launch<T>(s, qs, shots, src_elem, src_coef, amp + 5 * seg * L.C, R, rec_elem,
+                                           rec_coef, traces + seg * L.C * shots * R, fwork, dt, ns, wpb, st);
       if (rc != BBDG_OK) return rc;
     }
     const hipError_t le = launch_misfit<T>(steps * shots * R, traces, obs, J, st);
@@ -595,15 +648,17 @@ int misfit_typed(bbdg_solver* s, int64_t shots, const T* q0, const int32_t* src_
     a.qalt = fwork + n;
     a.shots = shots;
     a.nstages = 5 * ns;
-    a.t0 = t0 + (double)(seg * L.C) * dt;
     a.dtd = dt;
     a.src_elem = src_elem;
     a.src_coef = src_coef;
-    a.f0 = f0;
-    a.tshift = ts;
+    a.amp = amp + 5 * seg * L.C;
     a.rec_p = rec_p;
     a.rec_j = rec_j;
-    const hipError_t e = launch_batched<T>(s->N, wpb, a, st);
+    a.sync = s->d_sync;
+    a.barrier_timeout = barrier_ticks(s);
+    hipError_t e = launch_barrier_reset(s->d_sync, st);
+    if (e != hipSuccess) return hip_fail(e, BBDG_E_LAUNCH);
+    e = launch_batched<T>(s->N, wpb, a, st);
     if (e == hipErrorCooperativeLaunchTooLarge || e == hipErrorInvalidConfiguration) return hip_fail(e, BBDG_E_RESIDENT);
     if (e != hipSuccess) return hip_fail(e, BBDG_E_LAUNCH);
     for (int64_t it = ns - 1; it >= 0; --it) {
@@ -639,7 +694,8 @@ int misfit_typed(bbdg_solver* s, int64_t shots, const T* q0, const int32_t* src_
       }
     }
   }
-  const hipError_t le = launch_gradient_finalize(s->K, shots, s->d_geo, s->d_etoe, s->d_etofo, gk, gt, grad, st);
+  hipError_t le = launch_gradient_finalize(s->K, shots, s->d_geo, s->d_etoe, s->d_etofo, gk, gt, grad, st);
+  if (le == hipSuccess) le = launch_poison<double>(s->d_sync, grad, s->K, st);
   if (le != hipSuccess) return hip_fail(le, BBDG_E_LAUNCH);
   return BBDG_OK;
 }
@@ -661,6 +717,7 @@ const char* bbdg_strerror(int code) {
     case BBDG_E_MODE: return "unknown right-hand-side mode";
     case BBDG_E_OUTSIDE: return "point outside the mesh";
     case BBDG_E_RESIDENT: return "persistent grid cannot be co-resident";
+    case BBDG_E_TIMEOUT: return "grid barrier timed out (persistent grid not co-resident); results are NaN";
     default: return "unknown error code";
   }
 }
@@ -854,7 +911,9 @@ static int create_impl(bbdg_solver** out, int N, int dtype, int64_t K, const int
   bool ok = hipMalloc(&s->d_geo, dgeo.size() * sizeof(double)) == hipSuccess &&
             hipMalloc(&s->d_etoe, (size_t)(4 * K) * sizeof(int32_t)) == hipSuccess &&
             hipMalloc(&s->d_etofo, fo.size()) == hipSuccess &&
-            hipMalloc(&s->d_tab, tab.size() * sizeof(uint16_t)) == hipSuccess;
+            hipMalloc(&s->d_tab, tab.size() * sizeof(uint16_t)) == hipSuccess &&
+            hipMalloc(&s->d_sync, kSyncBytes) == hipSuccess;
+  ok = ok && hipMemset(s->d_sync, 0, kSyncBytes) == hipSuccess;
   ok = ok && hipMemcpy(s->d_geo, dgeo.data(), dgeo.size() * sizeof(double), hipMemcpyHostToDevice) == hipSuccess;
   ok = ok && hipMemcpy(s->d_etoe, EToE, (size_t)(4 * K) * sizeof(int32_t), hipMemcpyHostToDevice) == hipSuccess;
   ok = ok && hipMemcpy(s->d_etofo, fo.data(), fo.size(), hipMemcpyHostToDevice) == hipSuccess;
@@ -1039,7 +1098,7 @@ int bbdg_source_coeffs(const bbdg_solver* s, int64_t n, const int32_t* elem, con
 
 size_t bbdg_batched_work_bytes(const bbdg_solver* s, int64_t shots) {
   if (!s || shots < 1) return 0;
-  return 2 * (size_t)shots * 4 * (size_t)s->K * np_of(s->N) * elem_size(s->dtype);
+  return batched_fields_bytes(s, shots) + 5 * kStepsPerLaunch * sizeof(double);
 }
 
 int bbdg_run_batched(bbdg_solver* s, void* q, int64_t shots, const int32_t* src_elem, const void* src_coef, double f0,
@@ -1057,7 +1116,7 @@ int bbdg_run_batched(bbdg_solver* s, void* q, int64_t shots, const int32_t* src_
   const size_t bytes = (size_t)shots * 4 * (size_t)s->K * np_of(s->N) * elem_size(s->dtype);
   const char* a = (const char*)q;
   const char* w = (const char*)work;
-  if (a < w + 2 * bytes && w < a + bytes) return BBDG_E_ARG;
+  if (a < w + bbdg_batched_work_bytes(s, shots) && w < a + bytes) return BBDG_E_ARG;
   if (wpb == 0) wpb = (s->tuned_shots == shots && s->tuned_wpb) ? s->tuned_wpb : 4;
   if (steps == 0) return BBDG_OK;
   if (hipSetDevice(s->device) != hipSuccess) return BBDG_E_DEVICE;
@@ -1085,6 +1144,13 @@ int bbdg_tune_batched(bbdg_solver* s, int64_t shots, void* scratch, int* wpb, vo
     return BBDG_E_DEVICE;
   }
   const int cand[3] = {2, 4, 8};
+  // a timeout left by earlier runs is reported, not attributed to a candidate
+  const int pending = bbdg_status(s);
+  if (pending != BBDG_OK) {
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return pending;
+  }
   int best = 0, rc = BBDG_OK;
   float best_ms = 0.f;
   for (int c : cand) {
@@ -1106,6 +1172,12 @@ int bbdg_tune_batched(bbdg_solver* s, int64_t shots, void* scratch, int* wpb, vo
       rc = BBDG_E_DEVICE;
       break;
     }
+    rc = bbdg_status(s);
+    if (rc == BBDG_E_TIMEOUT) {  // the device did not keep this grid co-resident: not a candidate
+      rc = BBDG_OK;
+      continue;
+    }
+    if (rc != BBDG_OK) break;
     if (best == 0 || ms < best_ms) {
       best = c;
       best_ms = ms;
@@ -1118,6 +1190,23 @@ int bbdg_tune_batched(bbdg_solver* s, int64_t shots, void* scratch, int* wpb, vo
   s->tuned_shots = shots;
   s->tuned_wpb = best;
   *wpb = best;
+  return BBDG_OK;
+}
+
+int bbdg_status(bbdg_solver* s) {
+  if (!s || !s->d_sync) return BBDG_E_ARG;
+  if (hipSetDevice(s->device) != hipSuccess || hipDeviceSynchronize() != hipSuccess) return BBDG_E_DEVICE;
+  uint32_t* flag = s->d_sync + kSyncFlagWord;
+  uint32_t h = 0;
+  if (hipMemcpy(&h, flag, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess) return BBDG_E_DEVICE;
+  if (h == 0) return BBDG_OK;
+  if (hipMemset(flag, 0, sizeof(h)) != hipSuccess) return BBDG_E_DEVICE;
+  return BBDG_E_TIMEOUT;
+}
+
+int bbdg_set_barrier_timeout(bbdg_solver* s, double seconds) {
+  if (!s || !(seconds >= 0.0) || seconds > 3600.0) return BBDG_E_ARG;
+  s->barrier_seconds = seconds;
   return BBDG_OK;
 }
 

@@ -159,8 +159,8 @@ class Solver:
 
 
 class BatchedSolver:
-    """Independent shots on one mesh and wavespeed, advanced together in one
-    persistent kernel launch per run.
+    """Independent shots on one mesh and wavespeed, advanced together in
+    persistent kernel launches (up to 1024 steps each).
 
     sources: (S, 3) source positions (one Ricker point source per shot) or
     None; receivers: (R, 3) positions shared by all shots.  States are CUDA
@@ -254,6 +254,15 @@ class BatchedSolver:
                                       float(dt), int(steps), self.wpb, _stream_ptr(stream)), "bbdg_run_batched")
         return traces
 
+    def set_barrier_timeout(self, seconds):
+        """Longest wait at a grid barrier of the persistent launches (default 2 s)."""
+        check(load().bbdg_set_barrier_timeout(self.solver._h, float(seconds)), "bbdg_set_barrier_timeout")
+
+    def check(self):
+        """Waits for the device; raises BBDGError (BBDG_E_TIMEOUT) if a grid
+        barrier of a run since the last check timed out (outputs are NaN)."""
+        check(load().bbdg_status(self.solver._h), "batched run")
+
     def close(self):
         self.solver.close()
 
@@ -317,6 +326,10 @@ class Misfit:
                                           ctypes.c_void_p(self._work.data_ptr()), _stream_ptr(stream)),
               "bbdg_misfit_gradient")
         return g
+
+    def check(self):
+        """See BatchedSolver.check."""
+        self.batched.check()
 
     def close(self):
         self.batched.close()

@@ -156,6 +156,9 @@ def test_null_handles_and_strerror(lib):
     assert lib.bbdg_tune_batched(None, 1, None, None, None) == -1
     assert lib.bbdg_batched_work_bytes(None, 4) == 0
     assert lib.bbdg_source_coeffs(None, 0, None, None, None) == -1
+    assert lib.bbdg_status(None) == -1
+    assert lib.bbdg_set_barrier_timeout(None, 1.0) == -1
+    assert lib.bbdg_strerror(-12) != b"unknown error code"
 
 
 # -- host utilities of the batched path (no device involved) ---------------------

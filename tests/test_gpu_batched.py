@@ -40,12 +40,15 @@ def _case(N, n=2, drop_last=5, shots=4, nrec=5, seed=3):
     return P, mesh, c, prob, src, rec
 
 
+@pytest.mark.parametrize("wpb", [4])
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-@pytest.mark.parametrize("N", [1, 3, 4, 6])
-def test_batched_parity(N, dtype):
+@pytest.mark.parametrize("N", [1, 3, 4, 6, 8])
+def test_batched_parity(N, dtype, wpb, steps=7):
+    """N = 8 in FP64 with four waves per workgroup runs one element per
+    four-wave team; the other cases one wave per element group."""
     P, mesh, c, prob, src, rec = _case(N)
-    S, dt, steps, t0 = src.shape[0], 2e-3, 7, 0.08   # odd stage count: result in the second buffer
-    bs = P.BatchedSolver(N, mesh, c, S, sources=src, receivers=rec, f0=F0, ts=TS, dtype=dtype, wpb=4)
+    S, dt, t0 = src.shape[0], 2e-3, 0.08   # 7 steps, odd stage count: result in the second buffer
+    bs = P.BatchedSolver(N, mesh, c, S, sources=src, receivers=rec, f0=F0, ts=TS, dtype=dtype, wpb=wpb)
     # shot S-1 has no source but a nonzero initial state
     bs.src_elem[S - 1] = -1
     q0 = np.zeros((S, 4, prob.K, prob.Np))
@@ -66,7 +69,46 @@ def test_batched_parity(N, dtype):
         assert _rel(_host(q)[s], want_q[s]) < TOL[dtype], s
     assert tr.shape == (steps, S, len(rec))
     assert _rel(_host(tr), want_tr) < TOL[dtype]
+    bs.check()
     bs.close()
+
+
+def test_barrier_timeout_drains_and_reports():
+    """A zero barrier time limit (forced from the host) times every grid
+    barrier out: the launch still ends, q and the traces come back NaN, the
+    status reports BBDG_E_TIMEOUT once, and a run with the default limit is
+    then correct again."""
+    P, mesh, c, prob, src, rec = _case(3)
+    S, dt, steps = src.shape[0], 2e-3, 3
+    bs = P.BatchedSolver(3, mesh, c, S, sources=src, receivers=rec, f0=F0, ts=TS, dtype="f64", wpb=4)
+    bs.set_barrier_timeout(0.0)
+    q = bs.empty_state()
+    tr = bs.run(q, dt, steps, t0=0.1)
+    with pytest.raises(P.BBDGError) as err:
+        bs.check()
+    assert err.value.code == -12
+    assert np.isnan(_host(q)).all() and np.isnan(_host(tr)).all()
+    bs.check()   # the flag was cleared
+    bs.set_barrier_timeout(2.0)
+    q = bs.empty_state()
+    tr = bs.run(q, dt, steps, t0=0.1)
+    bs.check()
+    se, sl = prob.locate(src)
+    re, rl = prob.locate(rec)
+    want_q, want_tr = prob.run_shots(np.zeros((S, 4, prob.K, prob.Np)), dt, steps, se, sl, F0, TS, re, rl, t0=0.1)
+    assert _rel(_host(q), want_q) < TOL["f64"]
+    bs.close()
+
+
+def test_batched_parity_n8_one_wave_per_element():
+    """N = 8 FP64 with two waves per workgroup: one wave per element."""
+    test_batched_parity(8, "f64", 2)
+
+
+def test_batched_parity_across_launches():
+    """1027 steps: two persistent launches (1024 steps, then 3), each with its
+    own wavelet table; the second ends on an odd stage count."""
+    test_batched_parity(1, "f64", 4, steps=1027)
 
 
 def test_launch_shapes_agree_bitwise():
@@ -126,6 +168,7 @@ def test_c4_full_size_sampled():
     steps, t0, dt = 2, 0.1, cfg["dt"]
     q = bs.empty_state()
     tr = bs.run(q, dt, steps, t0=t0)
+    bs.check()
     qh = _host(q)
     prob = dg.Problem(VX, EToV, cfg["N"], c)
     se, sl = prob.locate(src)
