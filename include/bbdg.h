@@ -255,7 +255,8 @@ int bbdg_tune_batched(bbdg_solver* s, int64_t shots, void* scratch, int* wpb, vo
  * weights tau_p = 2/(c- + c+), tau_u = (c- + c+)/2 and of the source vector
  * on m.  States use the solver's element type; gradient sums are FP64.
  * The forward states are kept at checkpoints every ckpt_every steps (0 = only
- * the initial state) and each segment is recomputed once, recording its
+ * the initial state); the forward run records the stages of its last
+ * segment, and every other segment is recomputed once, recording its
  * stages, during the reverse sweep. */
 
 /* Replaces the wavespeed (host, K doubles, c > 0) of a solver; the mesh is

@@ -78,7 +78,7 @@ __host__ __device__ constexpr int a_item_stride(int cnt, int groups) {
 template <int N, typename T>
 struct AOcc {
   static constexpr int f64[10] = {0, 2, 3, 3, 4, 4, 3, 3, 2, 2};
-  static constexpr int f32[10] = {0, 3, 3, 4, 5, 5, 4, 4, 3, 3};
+  static constexpr int f32[10] = {0, 3, 3, 4, 6, 6, 4, 4, 3, 3};
   static constexpr int value = sizeof(T) == 8 ? f64[N] : f32[N];
 };
 
@@ -144,7 +144,7 @@ void bb_adjoint_kernel(AdjointArgs<T> A) {
   __shared__ uint16_t t_rsp[Np][3];
   __shared__ T t_rsc[3][Np];
 
-  __shared__ T su[WPB][E][4][Np];       // u = rb + b_s qb
+  __shared__ T su[WPB][E][1][Np];       // u_p of u = rb + b_s qb (the velocity enters through sh)
   __shared__ T sh[WPB][E][4][Np];       // h_i = grad(lambda_i) . u_vel
   __shared__ APair<T> slev[WPB][E][FB][Np];  // layered face vectors (p, velocity) pairs
   __shared__ APair<T> sfl[WPB][E][FB][Nfp];  // L^{fT} results on the face nodes
@@ -209,7 +209,7 @@ void bb_adjoint_kernel(AdjointArgs<T> A) {
   }
   __syncthreads();
 
-  const int lane = tid & 63;
+  const int lane0 = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int64_t K = A.K;
   const int64_t KNp = K * Np;
@@ -222,10 +222,14 @@ void bb_adjoint_kernel(AdjointArgs<T> A) {
 
   int64_t g = g_lo + (int64_t)(blockIdx.x >> 3) * WPB + w;
   AHeader<N, T> hd;
-  if (g < g_hi) load_aheader<N, T>(hd, A, (int64_t)((uint32_t)g % (uint32_t)G) * E, lane);
+  if (g < g_hi) load_aheader<N, T>(hd, A, (int64_t)__builtin_amdgcn_readfirstlane((uint32_t)g % (uint32_t)G) * E, lane0);
 
   for (; g < g_hi; g += wstride) {
-    const int64_t shot = (int64_t)((uint32_t)g / (uint32_t)G);
+    // lane-derived addresses are recomputed per group rather than hoisted
+    // out of the loop (where they would hold registers for its whole life)
+    int lane = lane0;
+    asm volatile("" : "+v"(lane));
+    const int64_t shot = (int64_t)__builtin_amdgcn_readfirstlane((uint32_t)g / (uint32_t)G);
     const int64_t e0 = (g - shot * G) * E;
     const int64_t sb = shot * 4 * KNp;
     const int64_t zb = shot * K * 8 * Nfp;
@@ -247,7 +251,7 @@ void bb_adjoint_kernel(AdjointArgs<T> A) {
     }
     wave_sync();
     if (g + wstride < g_hi)
-      load_aheader<N, T>(hd, A, (int64_t)((uint32_t)(g + wstride) % (uint32_t)G) * E, lane);
+      load_aheader<N, T>(hd, A, (int64_t)__builtin_amdgcn_readfirstlane((uint32_t)(g + wstride) % (uint32_t)G) * E, lane);
 
     // ---- issue every load of this group together --------------------------------
     // own adjoint state and recorded pressure right-hand side
@@ -274,7 +278,7 @@ void bb_adjoint_kernel(AdjointArgs<T> A) {
       const int v = lane + 64 * r;
       zq[r][0] = zq[r][1] = rjv[r][0] = rjv[r][1] = 0;
       if (v >= E * 4 * Nfp) continue;
-      const int el = v / (4 * Nfp);
+      const int el = E == 1 ? 0 : v / (4 * Nfp);
       const int rem = v - el * 4 * Nfp;
       const int f = rem / Nfp;
       const int gg = rem - f * Nfp;
@@ -351,7 +355,7 @@ void bb_adjoint_kernel(AdjointArgs<T> A) {
       for (int r = 0; r < NFI; ++r) {
         const int v = lane + 64 * r;
         if (v >= E * 4 * Nfp) continue;
-        const int el = v / (4 * Nfp);
+        const int el = E == 1 ? 0 : v / (4 * Nfp);
         const int rem = v - el * 4 * Nfp;
         const int f = rem / Nfp;
         const int gg = rem - f * Nfp;
@@ -365,7 +369,7 @@ void bb_adjoint_kernel(AdjointArgs<T> A) {
       for (int r = 0; r < NPL; ++r) {
         const int v = lane + 64 * r;
         if (v >= E * Np) continue;
-        const int el = v / Np;
+        const int el = E == 1 ? 0 : v / Np;
         const int n = v - el * Np;
         const uint32_t ap = t_alpha[n];
 #pragma unroll
@@ -389,13 +393,11 @@ void bb_adjoint_kernel(AdjointArgs<T> A) {
       const int v = lane + 64 * r;
       kpart[r] = 0;
       if (v >= E * Np) continue;
-      const int el = v / Np;
+      const int el = E == 1 ? 0 : v / Np;
       const int n = v - el * Np;
 #pragma unroll
-      for (int f = 0; f < 4; ++f) {
-        uv[r][f] += b_s * qv[r][f];
-        su[w][el][f][n] = uv[r][f];
-      }
+      for (int f = 0; f < 4; ++f) uv[r][f] += b_s * qv[r][f];
+      su[w][el][0][n] = uv[r][0];
       const T* ge = sgeo[w][el];
 #pragma unroll
       for (int i = 0; i < 4; ++i) sh[w][el][i][n] = ge[3 * i] * uv[r][1] + ge[3 * i + 1] * uv[r][2] + ge[3 * i + 2] * uv[r][3];
@@ -411,7 +413,7 @@ void bb_adjoint_kernel(AdjointArgs<T> A) {
       for (int f = 0; f < 4; ++f) acc[r][f] = 0;
       const int v = lane + 64 * r;
       if (v >= E * Np) continue;
-      const int el = v / Np;
+      const int el = E == 1 ? 0 : v / Np;
       const int n = v - el * Np;
       const uint32_t ap = t_alpha[n];
       const int bi[4] = {(int)(ap & 255), (int)((ap >> 8) & 255), (int)((ap >> 16) & 255), (int)(ap >> 24)};
@@ -448,7 +450,7 @@ void bb_adjoint_kernel(AdjointArgs<T> A) {
       for (int r = 0; r < NPL; ++r) {
         const int v = lane + 64 * r;
         if (v >= E * Np) continue;
-        const int el = v / Np;
+        const int el = E == 1 ? 0 : v / Np;
         const int n = v - el * Np;
         const uint32_t ap = t_alpha[n];
 #pragma unroll
@@ -502,7 +504,7 @@ void bb_adjoint_kernel(AdjointArgs<T> A) {
       for (int r = 0; r < NFI; ++r) {
         const int v = lane + 64 * r;
         if (v >= E * 4 * Nfp) continue;
-        const int el = v / (4 * Nfp);
+        const int el = E == 1 ? 0 : v / (4 * Nfp);
         const int rem = v - el * 4 * Nfp;
         const int f = rem / Nfp;
         const int gg = rem - f * Nfp;
@@ -537,6 +539,8 @@ void bb_adjoint_kernel(AdjointArgs<T> A) {
         sface[w][el][f][2][gg] = tau;
       }
       wave_sync();
+      // (independent LDS reads feeding one add chain beat a shuffle tree of
+      // dependent LDS round trips here)
       for (int v = lane; v < E * FB; v += 64) {
         const int el = v / FB, fl = v - el * FB;
         double t = 0.0;
@@ -551,7 +555,7 @@ void bb_adjoint_kernel(AdjointArgs<T> A) {
     for (int r = 0; r < NPL; ++r) {
       const int v = lane + 64 * r;
       if (v >= E * Np) continue;
-      const int el = v / Np;
+      const int el = E == 1 ? 0 : v / Np;
       const int n = v - el * Np;
       const uint32_t ap = t_alpha[n];
 #pragma unroll
@@ -572,7 +576,7 @@ void bb_adjoint_kernel(AdjointArgs<T> A) {
     for (int r = 0; r < NPL; ++r) {
       const int v = lane + 64 * r;
       if (v >= E * Np) continue;
-      const int el = v / Np;
+      const int el = E == 1 ? 0 : v / Np;
       const int n = v - el * Np;
       su[w][el][0][n] = kpart[r];
     }
@@ -600,7 +604,7 @@ void bb_adjoint_kernel(AdjointArgs<T> A) {
 #pragma unroll
     for (int r = 0; r < NPL; ++r) {
       const int v = lane + 64 * r;
-      const int el = v / Np;
+      const int el = E == 1 ? 0 : v / Np;
       if (v >= E * Np || e0 + el >= K) continue;
 #pragma unroll
       for (int f = 0; f < 4; ++f) {

@@ -33,6 +33,8 @@ struct bbdg_solver {
   std::vector<int32_t> h_etoe;       // K x 4
   int64_t tuned_shots = 0;           // shot count bbdg_tune_batched ran for
   int tuned_wpb = 0;                 // and the waves per workgroup it chose
+  const void* rec_work = nullptr;    // misfit work space whose stage records hold
+  int64_t rec_seg = -1;              // this segment (-1: none)
 };
 
 namespace {
@@ -480,11 +482,13 @@ size_t batched_fields_bytes(const bbdg_solver* s, int64_t shots) {
 }
 
 // One persistent launch of `steps` steps; amp holds the wavelet at each of
-// its 5 * steps stages (unused without sources).
+// its 5 * steps stages (unused without sources).  With rec_p and rec_j the
+// launch also records every stage for the adjoint.
 template <typename T>
 int run_batched_launch(bbdg_solver* s, T* q, int64_t shots, const int32_t* src_elem, const T* src_coef,
                        const double* amp, int R, const int32_t* rec_elem, const T* rec_coef, T* traces, T* work,
-                       double dt, int64_t steps, int wpb, hipStream_t st) {
+                       double dt, int64_t steps, int wpb, hipStream_t st, T* rec_p = nullptr,
+                       T* rec_j = nullptr) {
   const int64_t n = 4 * s->K * (int64_t)np_of(s->N);
   StageArgs<T> a = base_args<T>(s);
   a.qin = q;
@@ -501,6 +505,8 @@ int run_batched_launch(bbdg_solver* s, T* q, int64_t shots, const int32_t* src_e
   a.rec_elem = rec_elem;
   a.rec_coef = rec_coef;
   a.traces = traces;
+  a.rec_p = rec_p;
+  a.rec_j = rec_j;
   a.sync = s->d_sync;
   a.barrier_timeout = barrier_ticks(s);
   hipError_t e = launch_barrier_reset(s->d_sync, st);
@@ -602,11 +608,14 @@ int misfit_typed(bbdg_solver* s, int64_t shots, const T* q0, const int32_t* src_
   T* traces = (T*)(work + L.traces);
   const int wpb = (s->tuned_shots == shots && s->tuned_wpb) ? s->tuned_wpb : 4;
   double* amp = (double*)(work + L.amp);  // wavelet at every stage of the run
+  T* rec_p = (T*)(work + L.rec_p);
+  T* rec_j = (T*)(work + L.rec_j);
   if (src_elem) {
     const hipError_t e = launch_wavelet(amp, 5 * steps, t0, 0, dt, f0, ts, st);
     if (e != hipSuccess) return hip_fail(e, BBDG_E_LAUNCH);
   }
   if (forward) {
+    s->rec_seg = -1;
     if (q0) {
       if (hipMemcpyAsync(qs, q0, sbytes, hipMemcpyDeviceToDevice, st) != hipSuccess) return BBDG_E_DEVICE;
     } else if (hipMemsetAsync(qs, 0, sbytes, st) != hipSuccess) {
@@ -615,17 +624,21 @@ int misfit_typed(bbdg_solver* s, int64_t shots, const T* q0, const int32_t* src_
     for (int64_t seg = 0; seg < L.nseg; ++seg) {
       const int64_t ns = std::min(L.C, steps - seg * L.C);
       if (hipMemcpyAsync(ckpt + seg * n, qs, sbytes, hipMemcpyDeviceToDevice, st) != hipSuccess) return BBDG_E_DEVICE;
+      // the last segment, the first one the reverse sweep needs, records its
+      // stages now instead of being recomputed
+      const bool last = seg == L.nseg - 1;
       const int rc = run_batched_launch<T>(s, qs, shots, src_elem, src_coef, amp + 5 * seg * L.C, R, rec_elem,
-                                           rec_coef, traces + seg * L.C * shots * R, fwork, dt, ns, wpb, st);
+                                           rec_coef, traces + seg * L.C * shots * R, fwork, dt, ns, wpb, st,
+                                           last ? rec_p : nullptr, last ? rec_j : nullptr);
       if (rc != BBDG_OK) return rc;
     }
+    s->rec_work = work;
+    s->rec_seg = L.nseg - 1;
     const hipError_t le = launch_misfit<T>(steps * shots * R, traces, obs, J, st);
     if (le != hipSuccess) return hip_fail(le, BBDG_E_LAUNCH);
   }
   if (!grad) return BBDG_OK;
 
-  T* rec_p = (T*)(work + L.rec_p);
-  T* rec_j = (T*)(work + L.rec_j);
   T* rb = (T*)(work + L.rb);
   T* qb = (T*)(work + L.qb);
   T* z[2] = {(T*)(work + L.z), (T*)(work + L.z) + shots * s->K * 8 * Nfp};
@@ -639,28 +652,18 @@ int misfit_typed(bbdg_solver* s, int64_t shots, const T* q0, const int32_t* src_
   bool first = true;
   for (int64_t seg = L.nseg - 1; seg >= 0; --seg) {
     const int64_t ns = std::min(L.C, steps - seg * L.C);
-    // recompute the segment from its checkpoint, recording every stage
-    if (hipMemcpyAsync(qs, ckpt + seg * n, sbytes, hipMemcpyDeviceToDevice, st) != hipSuccess) return BBDG_E_DEVICE;
-    StageArgs<T> a = base_args<T>(s);
-    a.qin = qs;
-    a.qout = qs;
-    a.res = fwork;
-    a.qalt = fwork + n;
-    a.shots = shots;
-    a.nstages = 5 * ns;
-    a.dtd = dt;
-    a.src_elem = src_elem;
-    a.src_coef = src_coef;
-    a.amp = amp + 5 * seg * L.C;
-    a.rec_p = rec_p;
-    a.rec_j = rec_j;
-    a.sync = s->d_sync;
-    a.barrier_timeout = barrier_ticks(s);
-    hipError_t e = launch_barrier_reset(s->d_sync, st);
-    if (e != hipSuccess) return hip_fail(e, BBDG_E_LAUNCH);
-    e = launch_batched<T>(s->N, wpb, a, st);
-    if (e == hipErrorCooperativeLaunchTooLarge || e == hipErrorInvalidConfiguration) return hip_fail(e, BBDG_E_RESIDENT);
-    if (e != hipSuccess) return hip_fail(e, BBDG_E_LAUNCH);
+    // recompute the segment from its checkpoint, recording every stage (the
+    // last segment was recorded by the forward run)
+    if (!(s->rec_work == work && s->rec_seg == seg)) {
+      if (hipMemcpyAsync(qs, ckpt + seg * n, sbytes, hipMemcpyDeviceToDevice, st) != hipSuccess)
+        return BBDG_E_DEVICE;
+      s->rec_seg = -1;
+      const int rc = run_batched_launch<T>(s, qs, shots, src_elem, src_coef, amp + 5 * seg * L.C, 0, nullptr,
+                                           nullptr, nullptr, fwork, dt, ns, wpb, st, rec_p, rec_j);
+      if (rc != BBDG_OK) return rc;
+      s->rec_work = work;
+      s->rec_seg = seg;
+    }
     for (int64_t it = ns - 1; it >= 0; --it) {
       const int64_t step = seg * L.C + it;
       const hipError_t le = launch_inject_receivers<T>(Np, s->K, shots, R, rec_elem, rec_coef,

@@ -277,11 +277,13 @@ class Misfit:
     tensor); gradient() then returns dJ/dm (K,) float64 for that m."""
 
     def __init__(self, N, mesh, m, shots, sources, receivers, d_obs, dt, steps, t0=0.0, f0=8.0, ts=0.125,
-                 ckpt_every=0, dtype="f32", bc="rigid", device=0):
+                 ckpt_every=0, dtype="f32", bc="rigid", device=0, tune=True):
         import torch
         m = np.asarray(m, dtype=np.float64)
         self.batched = BatchedSolver(N, mesh, np.sqrt(m), shots, sources=sources, receivers=receivers, f0=f0,
                                      ts=ts, dtype=dtype, bc=bc, device=device, wpb=4)
+        if tune:
+            self.batched.tune()   # the misfit runs use the handle's tuned launch shape
         s = self.batched.solver
         self.dt, self.steps, self.t0, self.ckpt = float(dt), int(steps), float(t0), int(ckpt_every)
         self.d_obs = d_obs.to(s.device, s.torch_dtype).contiguous()

@@ -54,6 +54,12 @@ def test_gradient_matches_oracle_fp64(N, ckpt, bc):
     g = mf.gradient().cpu().numpy()
     assert abs(J - J0) < 1e-12 * abs(J0), (J, J0)
     assert _rel(g, g0) < 1e-10, _rel(g, g0)
+    # a second gradient of the same forward run: the last segment, which the
+    # forward run recorded, is now recomputed (its records were overwritten
+    # by the earlier segments) with the same arithmetic
+    g2 = mf.gradient().cpu().numpy()
+    assert np.array_equal(g, g2)
+    mf.check()
     mf.close()
 
 
