@@ -130,6 +130,10 @@ void bb_adjoint_kernel(AdjointArgs<T> A) {
   constexpr int Np = S::Np, Nfp = S::Nfp, E = S::E, NPL = S::NPL, NFI = S::NFI;
   constexpr int FB = S::FB, WPB = S::WPB, GEO = S::GEO;
   constexpr TabLayout L = tab_layout(N);
+  // Per-element gradient sums: in FP64 (fewer waves per SIMD) shuffle
+  // butterflies are faster; in FP32 independent LDS reads feeding one add
+  // chain beat the butterfly's dependent LDS round trips.
+  constexpr bool kShuffleSums = E == 1 && sizeof(T) == 8;
 
   __shared__ uint16_t t_fnode[4 * Nfp];
   __shared__ uint16_t t_fperm[6 * Nfp];
@@ -539,15 +543,25 @@ void bb_adjoint_kernel(AdjointArgs<T> A) {
         sface[w][el][f][2][gg] = tau;
       }
       wave_sync();
-      // (independent LDS reads feeding one add chain beat a shuffle tree of
-      // dependent LDS round trips here)
-      for (int v = lane; v < E * FB; v += 64) {
-        const int el = v / FB, fl = v - el * FB;
-        double t = 0.0;
-        for (int gg = 0; gg < Nfp; ++gg) t += (double)sface[w][el][fb0 + fl][2][gg];
-        sred[w][el][1 + fb0 + fl] = t;
+      if constexpr (!kShuffleSums) {
+        for (int v = lane; v < E * FB; v += 64) {
+          const int el = v / FB, fl = v - el * FB;
+          double t = 0.0;
+          for (int gg = 0; gg < Nfp; ++gg) t += (double)sface[w][el][fb0 + fl][2][gg];
+          sred[w][el][1 + fb0 + fl] = t;
+        }
+        wave_sync();
       }
-      wave_sync();
+    }
+    if constexpr (kShuffleSums) {
+      // tau terms of the four faces (kept in sface by every batch): 16 lanes
+      // per face, then a butterfly over the 16
+      const int f = lane >> 4, j = lane & 15;
+      double t = 0.0;
+      for (int gg = j; gg < Nfp; gg += 16) t += (double)sface[w][0][f][2][gg];
+#pragma unroll
+      for (int m = 8; m >= 1; m >>= 1) t += __shfl_xor(t, m);
+      if (j == 0) sred[w][0][1 + f] = t;
     }
 
     // ---- own face contributions ---------------------------------------------------
@@ -572,19 +586,28 @@ void bb_adjoint_kernel(AdjointArgs<T> A) {
     }
 
     // ---- kappa part of the gradient: sum_n u_p P / kappa ------------------------------
+    if constexpr (kShuffleSums) {
+      double t = 0.0;  // lanes past the element hold zeros
 #pragma unroll
-    for (int r = 0; r < NPL; ++r) {
-      const int v = lane + 64 * r;
-      if (v >= E * Np) continue;
-      const int el = E == 1 ? 0 : v / Np;
-      const int n = v - el * Np;
-      su[w][el][0][n] = kpart[r];
-    }
-    wave_sync();
-    for (int el = lane; el < E; el += 64) {
-      double t = 0.0;
-      for (int n = 0; n < Np; ++n) t += (double)su[w][el][0][n];
-      sred[w][el][0] = t;
+      for (int r = 0; r < NPL; ++r) t += (double)kpart[r];
+#pragma unroll
+      for (int m = 32; m >= 1; m >>= 1) t += __shfl_xor(t, m);
+      if (lane == 0) sred[w][0][0] = t;
+    } else {
+#pragma unroll
+      for (int r = 0; r < NPL; ++r) {
+        const int v = lane + 64 * r;
+        if (v >= E * Np) continue;
+        const int el = E == 1 ? 0 : v / Np;
+        const int n = v - el * Np;
+        su[w][el][0][n] = kpart[r];
+      }
+      wave_sync();
+      for (int el = lane; el < E; el += 64) {
+        double t = 0.0;
+        for (int n = 0; n < Np; ++n) t += (double)su[w][el][0][n];
+        sred[w][el][0] = t;
+      }
     }
     wave_sync();
 #pragma unroll
