@@ -63,11 +63,12 @@ struct Shape {
   static constexpr int Np = np_of(N);
   static constexpr int Nfp = nfp_of(N);
   static constexpr int E = (Np <= 32) ? (64 / Np) : 1;    // elements per group
-  // waves that share one element group in the single-stage kernel (the whole
-  // workgroup when > 1); batched launches always use one wave per group
+  // waves that share one element group (the whole workgroup when > 1;
+  // batched launches form such teams only with TW waves per workgroup)
   // (measured: teams pay off only where one wave per group needs more than
-  // half the register file, N >= 8 in FP64)
-  static constexpr int TW = sizeof(T) == 8 ? (N >= 8 ? 4 : 1) : 1;
+  // half the register file, N >= 8 in FP64; three waves at N = 8 leave 27
+  // of 192 threads idle instead of 91 of 256)
+  static constexpr int TW = sizeof(T) == 8 ? (N >= 9 ? 4 : (N == 8 ? 3 : 1)) : 1;
   // faces per lift batch (bounds the LDS of the face vectors), for one-wave
   // teams and for workgroup teams
   static constexpr int FB1 = sizeof(T) == 8 ? (N >= 8 ? 1 : (N >= 6 ? 2 : 4)) : (N >= 8 ? 2 : 4);

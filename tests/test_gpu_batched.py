@@ -42,9 +42,9 @@ def _case(N, n=2, drop_last=5, shots=4, nrec=5, seed=3):
 
 @pytest.mark.parametrize("wpb", [4])
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-@pytest.mark.parametrize("N", [1, 3, 4, 6, 8])
+@pytest.mark.parametrize("N", [1, 3, 4, 6, 8, 9])
 def test_batched_parity(N, dtype, wpb, steps=7):
-    """N = 8 in FP64 with four waves per workgroup runs one element per
+    """N = 9 in FP64 with four waves per workgroup runs one element per
     four-wave team; the other cases one wave per element group."""
     P, mesh, c, prob, src, rec = _case(N)
     S, dt, t0 = src.shape[0], 2e-3, 0.08   # 7 steps, odd stage count: result in the second buffer
@@ -68,7 +68,12 @@ def test_batched_parity(N, dtype, wpb, steps=7):
     for s in range(S):
         assert _rel(_host(q)[s], want_q[s]) < TOL[dtype], s
     assert tr.shape == (steps, S, len(rec))
-    assert _rel(_host(tr), want_tr) < TOL[dtype]
+    # a trace is a linear functional sum_n W_rn p_n whose terms cancel (by a
+    # factor of several hundred at N = 9 on this rough initial state), so its
+    # error is bounded relative to sum_n |W_rn| |p_n|, not to the trace
+    W = prob.receiver_weights(rl)
+    scale = max(float(np.sum(np.abs(W[r] * want_q[s, 0, re[r]]))) for s in range(S) for r in range(len(re)))
+    assert np.abs(_host(tr) - want_tr).max() < TOL[dtype] * scale
     bs.check()
     bs.close()
 
@@ -100,9 +105,9 @@ def test_barrier_timeout_drains_and_reports():
     bs.close()
 
 
-def test_batched_parity_n8_one_wave_per_element():
-    """N = 8 FP64 with two waves per workgroup: one wave per element."""
-    test_batched_parity(8, "f64", 2)
+def test_batched_parity_n9_one_wave_per_element():
+    """N = 9 FP64 with two waves per workgroup: one wave per element."""
+    test_batched_parity(9, "f64", 2)
 
 
 def test_batched_parity_across_launches():
