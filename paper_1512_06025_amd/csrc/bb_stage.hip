@@ -1,12 +1,13 @@
 // Fused Bernstein-Bezier DG stage kernel for gfx950 (wave64).
 //
-// Work decomposition.  A workgroup holds WPB = 4 independent wavefronts.  Each
-// wavefront owns E consecutive elements at a time (E = 64/Np for Np <= 32,
-// otherwise 1) and loops over element groups (persistent grid).  The waves of
-// a workgroup share the order's index tables, loaded into LDS once; after
-// that a wave only synchronises with itself (LDS operations of a wavefront
-// complete in issue order, so an LDS-only fence plus a wave barrier orders
-// them while global loads stay in flight).  Consecutive workgroups land on
+// Work decomposition.  A workgroup holds WPB = 4 independent wavefronts (or,
+// for the FP64 orders listed at Shape::TW, one team of TW waves).  Each team
+// owns E consecutive elements at a time (E = its threads / Np, at least 1)
+// and loops over element groups (persistent grid).  The waves of a
+// workgroup share the order's index tables, loaded into LDS once; after that
+// a one-wave team only synchronises with itself (LDS operations of a
+// wavefront complete in issue order, so an LDS-only fence plus a wave
+// barrier orders them while global loads stay in flight).  Consecutive workgroups land on
 // different XCDs, so the element range is split into 8 contiguous parts, one
 // per XCD, and each XCD's waves stride through their part: neighbouring
 // elements are processed by the same XCD at about the same time and their
@@ -62,18 +63,18 @@ template <int N, typename T>
 struct Shape {
   static constexpr int Np = np_of(N);
   static constexpr int Nfp = nfp_of(N);
-  static constexpr int E = (Np <= 32) ? (64 / Np) : 1;    // elements per group
   // waves that share one element group (the whole workgroup when > 1;
   // batched launches form such teams only with TW waves per workgroup)
   // (measured: teams pay off only where one wave per group needs more than
-  // half the register file, N >= 8 in FP64; three waves at N = 8 leave 27
-  // of 192 threads idle instead of 91 of 256)
-  static constexpr int TW = sizeof(T) == 8 ? (N >= 9 ? 4 : (N == 8 ? 3 : 1)) : 1;
+  // half the register file, N >= 8 in FP64, or where they fill the lanes:
+  // three waves at N = 8 leave 27 of 192 threads idle instead of 91 of 256,
+  // four waves at N = 6 hold three elements, 252 of 256 nodes, where one
+  // wave per element fills 84 of 128)
+  static constexpr int TW = sizeof(T) == 8 ? (N >= 9 ? 4 : (N == 8 ? 3 : (N == 6 ? 4 : 1))) : 1;
   // faces per lift batch (bounds the LDS of the face vectors), for one-wave
   // teams and for workgroup teams
   static constexpr int FB1 = sizeof(T) == 8 ? (N >= 8 ? 1 : (N >= 6 ? 2 : 4)) : (N >= 8 ? 2 : 4);
   static constexpr int FBT = 2;
-  static constexpr int HG = E * kGeoStride;               // header doubles per group
   // per-element derived geometry (type T): grad lambda_0..3 (12), kappa, pad,
   // then per face f at 16 + 6 f: g_x, g_y, g_z, a_p, a_u, b_u with
   //   sp = a_p [[p]] - a_u g.[[u]],  su = b_u g.[[u]] - [[p]]/2.
@@ -100,11 +101,13 @@ template <int N, typename T, int TW>
 struct Team {
   using S = Shape<N, T>;
   static constexpr int TPE = 64 * TW;
-  static constexpr int NPL = (S::E * S::Np + TPE - 1) / TPE;      // nodes per thread
-  static constexpr int SF = item_stride(S::Nfp, S::E * 4, TPE);   // face-item position stride
-  static constexpr int NFI = (S::E * 4 * SF + TPE - 1) / TPE;      // face items per thread
-  static constexpr int NHG = (S::HG + TPE - 1) / TPE;
-  static constexpr int NHE = (S::E * 4 + TPE - 1) / TPE;
+  static constexpr int E = TPE / S::Np > 1 ? TPE / S::Np : 1;    // elements per group
+  static constexpr int HG = E * kGeoStride;                       // header doubles per group
+  static constexpr int NPL = (E * S::Np + TPE - 1) / TPE;         // nodes per thread
+  static constexpr int SF = item_stride(S::Nfp, E * 4, TPE);      // face-item position stride
+  static constexpr int NFI = (E * 4 * SF + TPE - 1) / TPE;        // face items per thread
+  static constexpr int NHG = (HG + TPE - 1) / TPE;
+  static constexpr int NHE = (E * 4 + TPE - 1) / TPE;
 };
 
 // Synchronisation of the threads that share an element group.  LDS operations
@@ -156,19 +159,19 @@ template <int N, typename T, int TW>
 __device__ __forceinline__ void load_header(Header<N, T, TW>& h, const StageArgs<T>& A, int64_t g, int tl) {
   using S = Shape<N, T>;
   using M = Team<N, T, TW>;
-  const int64_t e0 = g * S::E;
+  const int64_t e0 = g * M::E;
 #pragma unroll
   for (int r = 0; r < M::NHG; ++r) {
     const int v = tl + M::TPE * r;
     int64_t idx = e0 * kGeoStride + v;
-    if (v >= S::HG || idx >= A.K * kGeoStride) idx = 0;
+    if (v >= M::HG || idx >= A.K * kGeoStride) idx = 0;
     h.geo[r] = A.geo[idx];
   }
 #pragma unroll
   for (int r = 0; r < M::NHE; ++r) {
     const int v = tl + M::TPE * r;
     int64_t idx = e0 * 4 + v;
-    if (v >= S::E * 4 || idx >= A.K * 4) idx = 0;
+    if (v >= M::E * 4 || idx >= A.K * 4) idx = 0;
     h.etoe[r] = A.etoe[idx];
     h.fo[r] = A.etofo[idx];
   }
@@ -266,7 +269,7 @@ void bb_stage_kernel(StageArgs<T> A) {
   static_assert(WPB % TW == 0 && (TW == 1 || TW == WPB), "a team is one wave or the whole workgroup");
   using M = Team<N, T, TW>;
   constexpr int TEAMS = WPB / TW, TPE = M::TPE;
-  constexpr int Np = S::Np, Nfp = S::Nfp, E = S::E, NPL = M::NPL, NFI = M::NFI;
+  constexpr int Np = S::Np, Nfp = S::Nfp, E = M::E, NPL = M::NPL, NFI = M::NFI;
   constexpr int FB = TW > 1 ? S::FBT : S::FB1, GEO = S::GEO;
   constexpr bool kUpdate = (MODE == kStage || kBatch);
   // FP32 up to N = 6 keeps (h_i, p) pairs per node (one 8-byte read per
@@ -424,7 +427,7 @@ void bb_stage_kernel(StageArgs<T> A) {
 #pragma unroll
     for (int r = 0; r < M::NHG; ++r) {
       const int v = lane + TPE * r;
-      if (v < S::HG) shg_w[v] = hd.geo[r];
+      if (v < M::HG) shg_w[v] = hd.geo[r];
     }
 #pragma unroll
     for (int r = 0; r < M::NHE; ++r) {
@@ -835,7 +838,8 @@ static hipError_t resident_grid(int64_t groups, int per_wg, int64_t* grid_out) {
 template <int N, typename T, int MODE>
 static hipError_t launch_one(const StageArgs<T>& a, hipStream_t stream) {
   using S = Shape<N, T>;
-  const int64_t groups = (a.K + S::E - 1) / S::E;
+  using M = Team<N, T, S::TW>;
+  const int64_t groups = (a.K + M::E - 1) / M::E;
   if (groups <= 0) return hipSuccess;
   constexpr int WPB = S::TW > 1 ? S::TW : 4;
   int64_t grid = 0;
@@ -848,8 +852,8 @@ static hipError_t launch_one(const StageArgs<T>& a, hipStream_t stream) {
 
 template <int N, typename T, int WPB, int MODE>
 static hipError_t launch_batched_mode(const StageArgs<T>& a, hipStream_t stream) {
-  using S = Shape<N, T>;
-  const int64_t groups = (a.K + S::E - 1) / S::E * a.shots;
+  using M = Team<N, T, team_waves<N, T, MODE, WPB>()>;
+  const int64_t groups = (a.K + M::E - 1) / M::E * a.shots;
   if (groups <= 0 || a.nstages <= 0) return hipSuccess;
   int64_t grid = 0;
   const hipError_t e = resident_grid<N, T, MODE, WPB>(groups, WPB / team_waves<N, T, MODE, WPB>(), &grid);
