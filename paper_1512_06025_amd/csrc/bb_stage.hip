@@ -65,12 +65,13 @@ struct Shape {
   static constexpr int Nfp = nfp_of(N);
   // waves that share one element group (the whole workgroup when > 1;
   // batched launches form such teams only with TW waves per workgroup)
-  // (measured: teams pay off only where one wave per group needs more than
-  // half the register file, N >= 8 in FP64, or where they fill the lanes:
-  // three waves at N = 8 leave 27 of 192 threads idle instead of 91 of 256,
-  // four waves at N = 6 hold three elements, 252 of 256 nodes, where one
-  // wave per element fills 84 of 128)
-  static constexpr int TW = sizeof(T) == 8 ? (N >= 9 ? 4 : (N == 8 ? 3 : (N == 6 ? 4 : 1))) : 1;
+  // (measured: teams pay off where one wave per group needs more than half
+  // the register file, N >= 8 in FP64, or where they fill the lanes: three
+  // waves at N = 8 leave 27 of 192 threads idle instead of 91 of 256; four
+  // waves hold seven elements at N = 4, 245 of 256 nodes, where one wave
+  // per element fills 35 of 64, and three at N = 6, 252 of 256 nodes, where
+  // one wave fills 84 of 128)
+  static constexpr int TW = (N == 4 || N == 6) ? 4 : (sizeof(T) == 8 ? (N >= 9 ? 4 : (N == 8 ? 3 : 1)) : 1);
   // faces per lift batch (bounds the LDS of the face vectors), for one-wave
   // teams and for workgroup teams
   static constexpr int FB1 = sizeof(T) == 8 ? (N >= 8 ? 1 : (N >= 6 ? 2 : 4)) : (N >= 8 ? 2 : 4);
