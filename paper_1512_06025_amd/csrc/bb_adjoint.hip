@@ -54,8 +54,10 @@ struct AShape {
   static constexpr int NHG = (HG + 63) / 64;
   static constexpr int NHE = (E * 4 + 63) / 64;
   // per element geometry (T): grad lambda_0..3 (12), kappa; per face f at
-  // 16 + 8 f: g (3), a_p, a_u, b_u, |g|, d(tau terms) packed below
-  static constexpr int GEO = 48;
+  // 16 + FS f: g (3), a_p, a_u, b_u, |g|, 1/|g|, -a_p/s, 1/(4|g|) (the
+  // reciprocals are taken once per face, not per face node)
+  static constexpr int FS = 12;
+  static constexpr int GEO = 16 + 4 * FS;
 };
 
 template <typename T>
@@ -128,7 +130,7 @@ __global__ __launch_bounds__((64 * AShape<N, T>::WPB)) __attribute__((amdgpu_wav
 void bb_adjoint_kernel(AdjointArgs<T> A) {
   using S = AShape<N, T>;
   constexpr int Np = S::Np, Nfp = S::Nfp, E = S::E, NPL = S::NPL, NFI = S::NFI;
-  constexpr int FB = S::FB, WPB = S::WPB, GEO = S::GEO;
+  constexpr int FB = S::FB, WPB = S::WPB, GEO = S::GEO, FS = S::FS;
   constexpr TabLayout L = tab_layout(N);
   // Per-element gradient sums: in FP64 (fewer waves per SIMD) shuffle
   // butterflies are faster; in FP32 independent LDS reads feeding one add
@@ -321,7 +323,7 @@ void bb_adjoint_kernel(AdjointArgs<T> A) {
       if (k >= K) {  // ragged tail: neutral geometry, no neighbours
         for (int c = 0; c < 3; ++c) o[3 * f + c] = 0;
         if (f == 0) o[12] = 1;
-        for (int c = 0; c < 8; ++c) o[16 + 8 * f + c] = 1;
+        for (int c = 0; c < FS; ++c) o[16 + FS * f + c] = 1;
         continue;
       }
       const double* ge = shg[w] + el * kGeoStride;
@@ -340,7 +342,7 @@ void bb_adjoint_kernel(AdjointArgs<T> A) {
       o[3 * f + 2] = (T)gz;
       if (f == 0) o[12] = (T)ge[9];
       const double F = 2.0 * sqrt(gx * gx + gy * gy + gz * gz);
-      T* fr = o + 16 + 8 * f;
+      T* fr = o + 16 + FS * f;
       fr[0] = (T)(-2.0 * gx);
       fr[1] = (T)(-2.0 * gy);
       fr[2] = (T)(-2.0 * gz);
@@ -348,7 +350,9 @@ void bb_adjoint_kernel(AdjointArgs<T> A) {
       fr[4] = (T)(0.5 * ge[9]);  // a_u = kappa / 2
       fr[5] = (T)ge[14 + f];     // b_u = s / (4 |g|)
       fr[6] = (T)F;
-      fr[7] = (T)0;
+      fr[7] = (T)(1.0 / F);
+      fr[8] = (T)(-ge[10 + f] / (4.0 * F * ge[14 + f]));  // -a_p / s, s = 4 |g| b_u
+      fr[9] = (T)(0.25 / F);
     }
     wave_sync();
 
@@ -366,7 +370,7 @@ void bb_adjoint_kernel(AdjointArgs<T> A) {
         // the neighbour's g is -(|g_nb|/|g_f|) g_f and zu carries |g_nb|:
         // the velocity adjoint gains -(g_f/|g_f|) zu
         sface[w][el][f][0][gg] = zq[r][0];
-        sface[w][el][f][1][gg] = -zq[r][1] / sgeo[w][el][16 + 8 * f + 6];
+        sface[w][el][f][1][gg] = -zq[r][1] * sgeo[w][el][16 + FS * f + 7];
       }
       wave_sync();
 #pragma unroll
@@ -380,7 +384,7 @@ void bb_adjoint_kernel(AdjointArgs<T> A) {
         for (int f = 0; f < 4; ++f) {
           if ((ap >> (8 * f)) & 255) continue;
           const int gg = t_proj[n][f];
-          const T* fr = sgeo[w][el] + 16 + 8 * f;
+          const T* fr = sgeo[w][el] + 16 + FS * f;
           const T cp = sface[w][el][f][0][gg], cu = sface[w][el][f][1][gg];
           qv[r][0] += dt * cp;
           qv[r][1] += dt * fr[0] * cu;
@@ -460,7 +464,7 @@ void bb_adjoint_kernel(AdjointArgs<T> A) {
 #pragma unroll
         for (int fl = 0; fl < FB; ++fl) {
           const int f = fb0 + fl;
-          const T* fr = sgeo[w][el] + 16 + 8 * f;
+          const T* fr = sgeo[w][el] + 16 + FS * f;
           const T ell = t_ell[(ap >> (8 * f)) & 255];
           const int pos = t_proj[n][f];
           slev[w][el][fl][pos] = APair<T>{ell * uv[r][0], ell * (fr[0] * uv[r][1] + fr[1] * uv[r][2] + fr[2] * uv[r][3])};
@@ -516,7 +520,7 @@ void bb_adjoint_kernel(AdjointArgs<T> A) {
         const int64_t k = e0 + el;
         T dp = 0, du = 0, tau = 0;
         if (k < K) {
-          const T* fr = sgeo[w][el] + 16 + 8 * f;
+          const T* fr = sgeo[w][el] + 16 + FS * f;
           const APair<T> zz = sfl[w][el][f - fb0][gg];
           const T zp = zz.p, zu = zz.u;
           // sp = a_p [[p]] - a_u g.[[u]],  su = b_u g.[[u]] - [[p]]/2
@@ -535,8 +539,7 @@ void bb_adjoint_kernel(AdjointArgs<T> A) {
             dp = (T)(-2) * jbp;
           }
           // d/ds of the flux at fixed jumps: -a_p/s [[p]] and g.[[u]]/(4|g|), s = 4 |g| b_u
-          const T s = (T)4 * fr[6] * fr[5];
-          tau = zp * (-fr[3] / s) * rjv[r][0] + zu * rjv[r][1] / ((T)4 * fr[6]);
+          tau = zp * fr[8] * rjv[r][0] + zu * rjv[r][1] * fr[9];
         }
         sface[w][el][f][0][gg] = dp;
         sface[w][el][f][1][gg] = du;
@@ -576,7 +579,7 @@ void bb_adjoint_kernel(AdjointArgs<T> A) {
       for (int f = 0; f < 4; ++f) {
         if ((ap >> (8 * f)) & 255) continue;
         const int gg = t_proj[n][f];
-        const T* fr = sgeo[w][el] + 16 + 8 * f;
+        const T* fr = sgeo[w][el] + 16 + FS * f;
         const T cp = sface[w][el][f][0][gg], cu = sface[w][el][f][1][gg];
         acc[r][0] += cp;
         acc[r][1] += fr[0] * cu;
