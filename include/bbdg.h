@@ -233,6 +233,9 @@ int bbdg_run_batched(bbdg_solver* s, void* q, int64_t shots, const int32_t* src_
 
 /* Autotuner of the batched launch shape: times two-step batched runs of
  * `shots` zero states for every wavefronts-per-workgroup candidate (2, 4, 8),
+ * which sets the elements per workgroup (one element group of 64/Np
+ * elements, at least one, per wave, or one workgroup team where the order
+ * has one of that size),
  * stores the fastest in the handle (used by bbdg_run_batched with wpb = 0)
  * and returns it in *wpb.  A candidate whose grid barrier times out (see
  * bbdg_status) or that cannot be co-resident is skipped.  Returns
