@@ -86,6 +86,10 @@ def test_barrier_timeout_drains_and_reports():
     P, mesh, c, prob, src, rec = _case(3)
     S, dt, steps = src.shape[0], 2e-3, 3
     bs = P.BatchedSolver(3, mesh, c, S, sources=src, receivers=rec, f0=F0, ts=TS, dtype="f64", wpb=4)
+    for bad in (-1.0, float("nan"), 1e9):
+        with pytest.raises(P.BBDGError) as err:
+            bs.set_barrier_timeout(bad)
+        assert err.value.code == -1
     bs.set_barrier_timeout(0.0)
     q = bs.empty_state()
     tr = bs.run(q, dt, steps, t0=0.1)
