@@ -21,6 +21,7 @@ struct StageArgs {
   T rk_a, rk_b, dt;
   int read_res;
   int bc;
+  int nt_store;  // 1: FP64 stage outputs with non-temporal stores (single-stage launches)
   // Batched multi-stage launches (mode kBatched): S shots stored shot-major
   // (S, 4, K, Np); stage s reads buffer s % 2 of {qout, qalt} and writes the
   // other; a Ricker point source per shot is added to the pressure equation;
@@ -134,6 +135,7 @@ struct NodalArgs {
   T rk_a, rk_b, dt;
   int read_res;
   int bc;
+  int nt_store;  // 1: FP64 stage outputs with non-temporal stores (single-stage launches)
 };
 
 template <typename T>

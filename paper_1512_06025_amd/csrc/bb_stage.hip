@@ -185,9 +185,18 @@ template <typename T>
 __device__ __forceinline__ T ld(const T* base, uint32_t idx) {
   return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + (idx * (uint32_t)sizeof(T)));
 }
-template <typename T>
+// Stores of the stage outputs; NT marks them non-temporal, which pays where
+// the fields do not fit in the last-level caches.  (A compile-time choice: a
+// run-time branch between the two stores is merged by the compiler into one
+// plain store.)
+template <bool NT, typename T>
 __device__ __forceinline__ void st(T* base, uint32_t idx, T x) {
-  *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + (idx * (uint32_t)sizeof(T))) = x;
+  T* p = reinterpret_cast<T*>(reinterpret_cast<char*>(base) + (idx * (uint32_t)sizeof(T)));
+  if constexpr (NT) {
+    __builtin_nontemporal_store(x, p);
+  } else {
+    *p = x;
+  }
 }
 
 // Carpenter-Kennedy (5,4) 2N-storage coefficients (batched runs step inside
@@ -260,7 +269,7 @@ constexpr int team_waves() {
   return (MODE >= kBatched && WPB != Shape<N, T>::TW) ? 1 : Shape<N, T>::TW;
 }
 
-template <int N, typename T, int MODE, int WPB>
+template <int N, typename T, int MODE, int WPB, bool NT = false>
 __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(Occ<N, T, team_waves<N, T, MODE, WPB>(), MODE >= kBatched>::value)))
 void bb_stage_kernel(StageArgs<T> A) {
   using S = Shape<N, T>;
@@ -727,12 +736,12 @@ void bb_stage_kernel(StageArgs<T> A) {
 #pragma unroll
         for (int f = 0; f < 4; ++f) {
           const T rs = dt * rhs[r][f] + rk_a * rv[r][f];
-          st(res_s + f * KNp, off, rs);
-          st(qout_s + f * KNp, off, qv[r][f] + rk_b * rs);
+          st<NT>(res_s + f * KNp, off, rs);
+          st<NT>(qout_s + f * KNp, off, qv[r][f] + rk_b * rs);
         }
       } else {
 #pragma unroll
-        for (int f = 0; f < 4; ++f) st(qout_s + f * KNp, off, rhs[r][f]);
+        for (int f = 0; f < 4; ++f) st<NT>(qout_s + f * KNp, off, rhs[r][f]);
       }
     }
   }  // element groups
@@ -810,7 +819,7 @@ hipError_t launch_poison(const uint32_t* sync, T* a, int64_t n, hipStream_t stre
 template hipError_t launch_poison<double>(const uint32_t*, double*, int64_t, hipStream_t);
 template hipError_t launch_poison<float>(const uint32_t*, float*, int64_t, hipStream_t);
 
-template <int N, typename T, int MODE, int WPB>
+template <int N, typename T, int MODE, int WPB, bool NT = false>
 static hipError_t resident_grid(int64_t groups, int per_wg, int64_t* grid_out) {
   static int resident = 0;  // co-resident workgroups per CU for this instantiation
   static int cus = 0;
@@ -819,7 +828,8 @@ static hipError_t resident_grid(int64_t groups, int per_wg, int64_t* grid_out) {
     if (hipGetDevice(&dev) != hipSuccess) return hipErrorInvalidDevice;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return hipErrorInvalidDevice;
     int occ = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, bb_stage_kernel<N, T, MODE, WPB>, 64 * WPB, 0) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, bb_stage_kernel<N, T, MODE, WPB, NT>, 64 * WPB, 0) !=
+        hipSuccess)
       return hipErrorInvalidValue;
     if (occ < 1) return hipErrorInvalidConfiguration;
     // persistent cooperative grids stay well inside the per-CU workgroup limit
@@ -836,19 +846,29 @@ static hipError_t resident_grid(int64_t groups, int per_wg, int64_t* grid_out) {
   return hipSuccess;
 }
 
-template <int N, typename T, int MODE>
-static hipError_t launch_one(const StageArgs<T>& a, hipStream_t stream) {
+template <int N, typename T, int MODE, bool NT>
+static hipError_t launch_one_nt(const StageArgs<T>& a, hipStream_t stream) {
   using S = Shape<N, T>;
   using M = Team<N, T, S::TW>;
   const int64_t groups = (a.K + M::E - 1) / M::E;
   if (groups <= 0) return hipSuccess;
   constexpr int WPB = S::TW > 1 ? S::TW : 4;
   int64_t grid = 0;
-  const hipError_t e = resident_grid<N, T, MODE, WPB>(groups, WPB / S::TW, &grid);
+  const hipError_t e = resident_grid<N, T, MODE, WPB, NT>(groups, WPB / S::TW, &grid);
   if (e != hipSuccess) return e;
   (void)hipGetLastError();  // drop errors left by earlier, unrelated calls
-  hipLaunchKernelGGL((bb_stage_kernel<N, T, MODE, WPB>), dim3((unsigned)grid), dim3(64 * WPB), 0, stream, a);
+  hipLaunchKernelGGL((bb_stage_kernel<N, T, MODE, WPB, NT>), dim3((unsigned)grid), dim3(64 * WPB), 0, stream, a);
   return hipGetLastError();
+}
+
+// Non-temporal output stores exist for the FP64 stage (the time-stepping
+// path); right-hand-side evaluations and FP32 use plain stores.
+template <int N, typename T, int MODE>
+static hipError_t launch_one(const StageArgs<T>& a, hipStream_t stream) {
+  if constexpr (MODE == kStage && sizeof(T) == 8) {
+    if (a.nt_store) return launch_one_nt<N, T, MODE, true>(a, stream);
+  }
+  return launch_one_nt<N, T, MODE, false>(a, stream);
 }
 
 template <int N, typename T, int WPB, int MODE>
