@@ -185,6 +185,13 @@ template <typename T>
 __device__ __forceinline__ T ld(const T* base, uint32_t idx) {
   return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + (idx * (uint32_t)sizeof(T)));
 }
+// Residual loads (read once, by the element itself): non-temporal with NT.
+template <bool NT, typename T>
+__device__ __forceinline__ T ldn(const T* base, uint32_t idx) {
+  const T* p = reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + (idx * (uint32_t)sizeof(T)));
+  if constexpr (NT) return __builtin_nontemporal_load(p); else return *p;
+}
+
 // Stores of the stage outputs; NT marks them non-temporal, which pays where
 // the fields do not fit in the last-level caches.  (A compile-time choice: a
 // run-time branch between the two stores is merged by the compiler into one
@@ -463,7 +470,7 @@ void bb_stage_kernel(StageArgs<T> A) {
       for (int f = 0; f < 4; ++f) qv[r][f] = ld(qin_f[f], noff[r]);
       if (kUpdate && read_res && !S::LATE_RES) {
 #pragma unroll
-        for (int f = 0; f < 4; ++f) rv[r][f] = ld(res_s + f * KNp, noff[r]);
+        for (int f = 0; f < 4; ++f) rv[r][f] = ldn<NT>(res_s + f * KNp, noff[r]);
       } else {
 #pragma unroll
         for (int f = 0; f < 4; ++f) rv[r][f] = 0;
@@ -593,7 +600,7 @@ void bb_stage_kernel(StageArgs<T> A) {
 #pragma unroll
         for (int r = 0; r < NPL; ++r) {
 #pragma unroll
-          for (int f = 0; f < 4; ++f) rv[r][f] = ld(res_s + f * KNp, noff[r]);
+          for (int f = 0; f < 4; ++f) rv[r][f] = ldn<NT>(res_s + f * KNp, noff[r]);
         }
       }
     }
