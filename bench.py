@@ -50,6 +50,17 @@ def recorded_traffic(kernel, workload):
     return None
 
 
+def stage_kernel_name(N, K):
+    """Name of the FP64 stage kernel instantiation the library launches for
+    order N on K elements: waves per workgroup (three at N = 8, else four)
+    and non-temporal output stores when the state, residual and second
+    buffer (3 x 4 K Np doubles) exceed the 256 MB last-level cache."""
+    Np = (N + 1) * (N + 2) * (N + 3) // 6
+    wpb = 3 if N == 8 else 4
+    nt = 3 * 4 * K * Np * 8 > 256 * 1024 * 1024
+    return "bb_stage_kernel<%d, double, 0, %d, %s>" % (N, wpb, "true" if nt else "false")
+
+
 def algorithmic_bytes_per_element(N, word):
     """w (16 Np + 16 Nfp + 14) + 20 bytes: read q and res, read the 4 faces'
     neighbour traces, write q and res; 14 words of geometry, 20 B of indices."""
@@ -288,8 +299,8 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": recorded_traffic("bb_stage_kernel<%d, double, 0, 4>" % N, args.config),
-            "kernel": "bb_stage_kernel<%d, double, 0, 4>" % N,
+            "traffic": recorded_traffic(stage_kernel_name(N, K), args.config),
+            "kernel": stage_kernel_name(N, K),
             "bytes_per_launch": bytes_launch,
             "avg_launch_us": stage_us,
         },
