@@ -2,7 +2,8 @@
 benchmark times.
 
 * c2 (24,576 jittered tets, N = 5): one LSRK4 step of bbdg_run against the
-  oracle on every coefficient, FP64 (1e-12) and FP32 (1e-5).
+  oracle on every coefficient, FP64 (1e-12) and FP32 (1e-5); the same mesh
+  at N = 7 in FP64, which takes the non-temporal-store instantiation.
 * c3 (196,608 tets, c ~ U[1,3], N = 1..9): one right-hand side of the whole
   mesh on the GPU, checked element by element on a seeded sample of
   elements.  The oracle evaluates the sample on a sub-mesh made of the
@@ -50,6 +51,24 @@ def test_c2_one_step(dtype):
     s.run(q, cfg["dt"], 1)
     want = prob.lsrk4(q0, cfg["dt"], 1)
     assert _rel(_host(q), want) < TOL[dtype]
+    s.close()
+
+
+def test_c2_mesh_n7_one_step_nontemporal_stores():
+    """N = 7 on the 24,576-tet mesh, FP64: the three field sets (270 MiB)
+    exceed the 256 MB last-level cache, so the stage runs the instantiation
+    with non-temporal output stores and residual loads; one LSRK4 step on
+    every coefficient against the oracle (1e-12)."""
+    import paper_1512_06025_amd as P
+    cfg, VX, EToV, c = workload.build_preset("c2", N=7)
+    prob = dg.Problem(VX, EToV, 7, c)
+    assert 3 * 4 * prob.K * prob.Np * 8 > 256 * 1024 * 1024
+    q0 = workload.random_coeffs(prob.K, prob.Np, seed=22)
+    s = P.Solver(7, P.mesh_geometry(VX, EToV), c, dtype="f64")
+    q = torch.from_numpy(q0).to("cuda", s.torch_dtype)
+    s.run(q, cfg["dt"], 1)
+    want = prob.lsrk4(q0, cfg["dt"], 1)
+    assert _rel(_host(q), want) < TOL["f64"]
     s.close()
 
 
