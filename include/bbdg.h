@@ -225,7 +225,9 @@ size_t bbdg_batched_work_bytes(const bbdg_solver* s, int64_t shots);
  *             bbdg_tune_batched chose for this shot count (4 if not tuned).
  * shots * ceil(K / E) must stay below 2^32 (E = elements per wavefront).
  * Fails with BBDG_E_RESIDENT, before anything runs, if the grid cannot be
- * co-resident. */
+ * co-resident.  Runs asynchronously on `stream`; a grid barrier that timed
+ * out while it ran (q and traces are then NaN) is reported by bbdg_status.
+ * Calls on one handle must not overlap (they share its barrier words). */
 int bbdg_run_batched(bbdg_solver* s, void* q, int64_t shots, const int32_t* src_elem,
                      const void* src_coef, double f0, double ts, int R, const int32_t* rec_elem,
                      const void* rec_coef, void* traces, void* work, double t0, double dt,
@@ -235,9 +237,8 @@ int bbdg_run_batched(bbdg_solver* s, void* q, int64_t shots, const int32_t* src_
  * `shots` zero states for every wavefronts-per-workgroup candidate (2, 4, 8),
  * which sets the elements per workgroup (one element group of 64/Np
  * elements, at least one, per wave, or one workgroup team where the order
- * has one of that size),
- * stores the fastest in the handle (used by bbdg_run_batched with wpb = 0)
- * and returns it in *wpb.  A candidate whose grid barrier times out (see
+ * has one of that size), stores the fastest in the handle (used by
+ * bbdg_run_batched with wpb = 0) and returns it in *wpb.  A candidate whose grid barrier times out (see
  * bbdg_status) or that cannot be co-resident is skipped.  Returns
  * BBDG_E_TIMEOUT, without tuning, if an earlier run of the handle left a
  * timeout unreported.  scratch: device, >= bbdg_batched_work_bytes(s,
@@ -302,10 +303,10 @@ int bbdg_destroy(bbdg_solver* s);
  * device to finish its work, then returns BBDG_E_TIMEOUT (and clears the
  * flag) if a grid-wide barrier of any such launch since the last call timed
  * out, else BBDG_OK.  Those barriers bound their wait (2 s unless
- * bbdg_set_barrier_timeout says otherwise): a grid
- * that the device does not keep co-resident ends every workgroup instead of
- * hanging, and the run's outputs (q and traces of bbdg_run_batched, J and
- * the gradient of the misfit calls) are filled with NaN. */
+ * bbdg_set_barrier_timeout says otherwise): a grid that the device does not
+ * keep co-resident ends every workgroup instead of hanging, and the run's
+ * outputs (q and traces of bbdg_run_batched, J and the gradient of the
+ * misfit calls) are filled with NaN. */
 int bbdg_status(bbdg_solver* s);
 
 /* Longest wait at a grid barrier of the handle's persistent launches, in
