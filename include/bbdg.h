@@ -161,6 +161,21 @@ size_t bbdg_work_bytes(const bbdg_solver* s);
 int bbdg_run(bbdg_solver* s, void* q, void* work, double t0, double dt, int64_t steps,
              void* stream);
 
+/* Output stores of the FP64 stage kernel that bbdg_run launches (a
+ * performance choice; the arithmetic and results are identical):
+ *   AUTO:        non-temporal stores (and residual loads) when the state,
+ *                residual and second buffer, 3 x 4 K Np doubles, exceed the
+ *                256 MB last-level cache of the MI355X, plain otherwise;
+ *   PLAIN:       always plain stores;
+ *   NONTEMPORAL: always non-temporal.
+ * FP32 solvers, nodal comparators and batched runs always use plain stores.
+ * The default is AUTO.  bbdg_set_store_policy fails with BBDG_E_ARG for an
+ * unknown policy; bbdg_nontemporal_stores returns 1 if bbdg_run on this
+ * handle uses the non-temporal variant, else 0 (BBDG_E_ARG for NULL). */
+enum { BBDG_STORES_AUTO = 0, BBDG_STORES_PLAIN = 1, BBDG_STORES_NONTEMPORAL = 2 };
+int bbdg_set_store_policy(bbdg_solver* s, int policy);
+int bbdg_nontemporal_stores(const bbdg_solver* s);
+
 /* ---- Batched shots: point sources and receivers ---------------------------
  * The paper's experiments have no forcing (f = 0 in Section 2); the batched
  * path adds the standard seismic source term to the pressure equation,

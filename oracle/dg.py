@@ -206,15 +206,19 @@ class Problem:
         """B_alpha(lambda_r) for receivers at barycentric points lam (R, 4)."""
         return bernstein_eval(self.N, np.atleast_2d(np.asarray(lam, dtype=np.float64)))
 
-    def run_shots(self, q0, dt, steps, src_elem, src_lam, f0, ts, rec_elem, rec_lam, t0=0.0):
+    def run_shots(self, q0, dt, steps, src_elem, src_lam, f0, ts, rec_elem, rec_lam, t0=0.0,
+                  trace_scales=False):
         """Independent shots, each with its own point source (src_elem[s] = -1:
         none), sharing the receivers.  q0: (S, 4, K, Np).  Returns the final
         states (S, 4, K, Np) and the traces (steps, S, R): the pressure at the
-        receivers after every step."""
+        receivers after every step.  With trace_scales=True also returns
+        sum_n |W_rn| |p_n| for every trace (steps, S, R): the size of the
+        terms each trace sums, which bounds its rounding error."""
         q0 = np.asarray(q0, dtype=np.float64)
         S, R = q0.shape[0], len(rec_elem)
         W = self.receiver_weights(rec_lam) if R else np.zeros((0, self.Np))
         traces = np.zeros((steps, S, R))
+        scales = np.zeros((steps, S, R))
         out = np.empty_like(q0)
         for s in range(S):
             forcing = None if src_elem[s] < 0 else self.point_source(src_elem[s], src_lam[s], f0, ts)
@@ -222,7 +226,10 @@ class Problem:
             def record(n, q, s=s):
                 for r in range(R):
                     traces[n - 1, s, r] = q[0, rec_elem[r]] @ W[r]
+                    scales[n - 1, s, r] = np.abs(q[0, rec_elem[r]]) @ np.abs(W[r])
             out[s] = self.lsrk4(q0[s], dt, steps, callback=record, forcing=forcing, t0=t0)
+        if trace_scales:
+            return out, traces, scales
         return out, traces
 
     def pressure_integral(self, q):

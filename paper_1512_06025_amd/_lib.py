@@ -13,6 +13,7 @@ LIB_PATH = os.path.join(HERE, "libbbdg.so")
 BBDG_F64, BBDG_F32 = 0, 1
 BBDG_BC_RIGID, BBDG_BC_PRESSURE_RELEASE = 0, 1
 BBDG_RHS_FULL, BBDG_RHS_VOLUME, BBDG_RHS_SURFACE = 0, 1, 2
+BBDG_STORES_AUTO, BBDG_STORES_PLAIN, BBDG_STORES_NONTEMPORAL = 0, 1, 2
 
 ERRORS = {
     0: "BBDG_OK", -1: "BBDG_E_ARG", -2: "BBDG_E_ORDER", -3: "BBDG_E_MESH",
@@ -42,6 +43,8 @@ SIGNATURES = {
     "bbdg_work_bytes": (_c.c_size_t, [_c.c_void_p]),
     "bbdg_run": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_double, _c.c_double,
                             _c.c_int64, _c.c_void_p]),
+    "bbdg_set_store_policy": (_c.c_int, [_c.c_void_p, _c.c_int]),
+    "bbdg_nontemporal_stores": (_c.c_int, [_c.c_void_p]),
     "bbdg_locate_points": (_c.c_int, [_c.c_int64, _c.c_int64, _c.c_void_p, _c.c_void_p, _c.c_int64,
                                       _c.c_void_p, _c.c_void_p, _c.c_void_p]),
     "bbdg_bernstein_eval": (_c.c_int, [_c.c_int, _c.c_int64, _c.c_void_p, _c.c_void_p]),

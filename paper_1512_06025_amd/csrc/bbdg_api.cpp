@@ -35,6 +35,7 @@ struct bbdg_solver {
   int tuned_wpb = 0;                 // and the waves per workgroup it chose
   const void* rec_work = nullptr;    // misfit work space whose stage records hold
   int64_t rec_seg = -1;              // this segment (-1: none)
+  int store_policy = BBDG_STORES_AUTO;  // output stores of the FP64 time-stepping stage
 };
 
 namespace {
@@ -141,13 +142,15 @@ int hip_fail(hipError_t e, int code) {
 
 // Non-temporal output stores for the FP64 stage when the three field sets a
 // run touches (state, residual, second buffer) exceed the 256 MB last-level
-// cache.  Measured on 196,608 tets: FP64 stages 1.4-4.9 % faster for
-// N = 4..9; where the fields fit (N = 5 on 24,576 tets) plain stores are
-// 9 % faster, and FP32 gains little or loses (N = 7, 9).  Batched launches
-// use plain stores.
+// cache (policy BBDG_STORES_AUTO).  Measured on 196,608 tets: FP64 stages
+// 1.4-4.9 % faster for N = 4..9; where the fields fit (N = 5 on 24,576 tets)
+// plain stores are 9 % faster, and FP32 gains little or loses (N = 7, 9), so
+// FP32 has no such variant.  Batched launches use plain stores.
 bool nt_stores(const bbdg_solver* s, int64_t shots) {
+  if (s->dtype != BBDG_F64 || s->basis != 0 || s->store_policy == BBDG_STORES_PLAIN) return false;
+  if (s->store_policy == BBDG_STORES_NONTEMPORAL) return true;
   const double field_bytes = 4.0 * (double)s->K * np_of(s->N) * (double)elem_size(s->dtype) * (double)shots;
-  return s->dtype == BBDG_F64 && 3.0 * field_bytes > 256.0 * 1024 * 1024;
+  return 3.0 * field_bytes > 256.0 * 1024 * 1024;
 }
 
 template <typename T>
@@ -1232,11 +1235,27 @@ int bbdg_set_wavespeed(bbdg_solver* s, const double* c) {
     if (!(c[k] > 0.0)) return BBDG_E_ARG;
   std::vector<double> dgeo;
   device_header(s, c, dgeo);
+  // stage records of a misfit run belong to the old wavespeed
+  s->rec_work = nullptr;
+  s->rec_seg = -1;
   if (hipSetDevice(s->device) != hipSuccess) return BBDG_E_DEVICE;
   if (hipDeviceSynchronize() != hipSuccess) return BBDG_E_DEVICE;
   if (hipMemcpy(s->d_geo, dgeo.data(), dgeo.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
     return BBDG_E_DEVICE;
   return BBDG_OK;
+}
+
+int bbdg_set_store_policy(bbdg_solver* s, int policy) {
+  if (!s) return BBDG_E_ARG;
+  if (policy != BBDG_STORES_AUTO && policy != BBDG_STORES_PLAIN && policy != BBDG_STORES_NONTEMPORAL)
+    return BBDG_E_ARG;
+  s->store_policy = policy;
+  return BBDG_OK;
+}
+
+int bbdg_nontemporal_stores(const bbdg_solver* s) {
+  if (!s) return BBDG_E_ARG;
+  return nt_stores(s, 1) ? 1 : 0;
 }
 
 size_t bbdg_misfit_work_bytes(const bbdg_solver* s, int64_t shots, int R, int64_t steps, int64_t ckpt_every) {

@@ -146,6 +146,19 @@ class Solver:
                               float(t0), float(dt), int(steps), _stream_ptr(stream)), "bbdg_run")
         return q
 
+    def set_store_policy(self, policy):
+        """"auto", "plain" or "nontemporal" output stores of the FP64 stage
+        (a performance choice; results are identical)."""
+        code = {"auto": _lib.BBDG_STORES_AUTO, "plain": _lib.BBDG_STORES_PLAIN,
+                "nontemporal": _lib.BBDG_STORES_NONTEMPORAL}[policy]
+        check(load().bbdg_set_store_policy(self._h, code), "bbdg_set_store_policy")
+
+    def nontemporal_stores(self):
+        """True if run() launches the non-temporal-store stage variant."""
+        r = load().bbdg_nontemporal_stores(self._h)
+        check(r if r < 0 else 0, "bbdg_nontemporal_stores")
+        return bool(r)
+
     def close(self):
         if getattr(self, "_h", None):
             load().bbdg_destroy(self._h)
@@ -274,7 +287,9 @@ class Misfit:
     d_obs: CUDA tensor (steps, S, R) of the solver's element type.  evaluate(m)
     sets the wavespeed to sqrt(m), runs the forward problem keeping
     checkpoints every ckpt_every steps, and returns J (0-dim float64 CUDA
-    tensor); gradient() then returns dJ/dm (K,) float64 for that m."""
+    tensor); gradient() then returns dJ/dm (K,) float64 at the model of the
+    last evaluate() (it needs that run's checkpoints).  `evaluations` counts
+    the forward runs of this object."""
 
     def __init__(self, N, mesh, m, shots, sources, receivers, d_obs, dt, steps, t0=0.0, f0=8.0, ts=0.125,
                  ckpt_every=0, dtype="f32", bc="rigid", device=0, tune=True):
@@ -295,6 +310,7 @@ class Misfit:
         self._work = torch.empty(nbytes // 8 + 32, dtype=torch.float64, device=s.device)
         self._J = torch.zeros((), dtype=torch.float64, device=s.device)
         self._evaluated = False
+        self.evaluations = 0
 
     def _args(self):
         b = self.batched
@@ -310,6 +326,7 @@ class Misfit:
         c = np.ascontiguousarray(np.sqrt(mh))
         check(load().bbdg_set_wavespeed(self.batched.solver._h, c.ctypes.data), "bbdg_set_wavespeed")
         self.batched.update_sources()
+        self._evaluated = False   # the checkpoints belong to the previous model
 
     def evaluate(self, m=None, stream=None):
         if m is not None:
@@ -317,6 +334,7 @@ class Misfit:
         check(load().bbdg_misfit(*self._args(), ctypes.c_void_p(self._J.data_ptr()),
                                  ctypes.c_void_p(self._work.data_ptr()), _stream_ptr(stream)), "bbdg_misfit")
         self._evaluated = True
+        self.evaluations += 1
         return self._J.clone()
 
     def gradient(self, stream=None):
@@ -343,17 +361,29 @@ def _misfit_function():
 
     class MisfitFunction(torch.autograd.Function):
         """J = MisfitFunction.apply(m, misfit): forward runs the forward
-        problem (checkpointed); backward runs the adjoint sweep, which
-        recomputes each segment from its checkpoint, and returns
+        problem (checkpointed) at m; backward runs the adjoint sweep at the
+        same m (re-running the forward problem first if the Misfit was
+        evaluated at another model in between), which recomputes each
+        segment from its checkpoint, and returns
         grad_output * dJ/dm."""
 
         @staticmethod
         def forward(ctx, m, misfit):
+            J = misfit.evaluate(m)
             ctx.misfit = misfit
-            return misfit.evaluate(m)
+            ctx.m = m.detach().clone()
+            ctx.evaluation = misfit.evaluations
+            return J
 
         @staticmethod
         def backward(ctx, grad_out):
-            return grad_out * ctx.misfit.gradient(), None
+            mf = ctx.misfit
+            # the gradient needs the checkpoints of a forward run at this
+            # graph's m; if the Misfit was evaluated since (another graph, a
+            # line search), run the forward problem at this m again first
+            if mf.evaluations != ctx.evaluation:
+                mf.evaluate(ctx.m)
+                ctx.evaluation = mf.evaluations
+            return grad_out * mf.gradient(), None
 
     return MisfitFunction

@@ -44,7 +44,8 @@ def _oracle(VX, EToV, m, src, rec, obs, N, bc="rigid", dt=2e-3, t0=0.08):
 
 
 @pytest.mark.parametrize("N,ckpt,bc", [(1, 0, "rigid"), (2, 0, "rigid"), (3, 4, "rigid"), (4, 1, "rigid"),
-                                       (5, 2, "rigid"), (3, 0, "pressure_release"), (6, 3, "rigid")])
+                                       (5, 2, "rigid"), (3, 0, "pressure_release"), (6, 3, "rigid"),
+                                       (7, 2, "rigid"), (8, 0, "rigid"), (9, 4, "pressure_release")])
 def test_gradient_matches_oracle_fp64(N, ckpt, bc):
     import paper_1512_06025_amd as P
     VX, EToV, m, src, rec, obs = _case(N)
@@ -90,6 +91,31 @@ def test_gradient_against_gpu_finite_differences():
         mm[k] -= eps
         fd = (float(mf.evaluate(mp).item()) - float(mf.evaluate(mm).item())) / (2 * eps)
         assert abs(fd - g[k]) < 1e-6 * abs(g[k]), (k, fd, g[k])
+    mf.close()
+
+
+def test_autograd_two_graphs_before_backward():
+    """Two forward evaluations at different models before either backward:
+    each backward returns the gradient at its own model (the Misfit re-runs
+    the forward problem when it was evaluated elsewhere in between)."""
+    import paper_1512_06025_amd as P
+    VX, EToV, m1, src, rec, obs = _case(2)
+    m2 = m1 * (1.0 + 0.2 * np.sin(np.arange(m1.size)))
+    mf = _gpu_misfit(P, VX, EToV, m1, src, rec, obs, 2, "f64", 2)
+    t1 = torch.tensor(m1, dtype=torch.float64, device="cuda", requires_grad=True)
+    t2 = torch.tensor(m2, dtype=torch.float64, device="cuda", requires_grad=True)
+    J1 = P.MisfitFunction.apply(t1, mf)
+    J2 = P.MisfitFunction.apply(t2, mf)
+    J1.backward()
+    J2.backward()
+    for t, m, J in ((t1, m1, J1), (t2, m2, J2)):
+        J0, g0 = _oracle(VX, EToV, m, src, rec, obs, 2)
+        assert abs(float(J.item()) - J0) < 1e-12 * abs(J0)
+        assert _rel(t.grad.cpu().numpy(), g0) < 1e-10
+    # a gradient after set_m without a new forward run is refused
+    mf.set_m(m1)
+    with pytest.raises(RuntimeError):
+        mf.gradient()
     mf.close()
 
 

@@ -63,17 +63,20 @@ def test_batched_parity(N, dtype, wpb, steps=7):
     np.testing.assert_array_equal(_host(bs.src_elem)[:-1], se[:-1])
     np.testing.assert_array_equal(_host(bs.rec_elem), re)
     se[-1] = -1
-    want_q, want_tr = prob.run_shots(q0, dt, steps, se, sl, F0, TS, re, rl, t0=t0)
+    want_q, want_tr, scale = prob.run_shots(q0, dt, steps, se, sl, F0, TS, re, rl, t0=t0, trace_scales=True)
     assert _rel(_host(q), want_q) < TOL[dtype]
     for s in range(S):
         assert _rel(_host(q)[s], want_q[s]) < TOL[dtype], s
     assert tr.shape == (steps, S, len(rec))
     # a trace is a linear functional sum_n W_rn p_n whose terms cancel (by a
-    # factor of several hundred at N = 9 on this rough initial state), so its
-    # error is bounded relative to sum_n |W_rn| |p_n|, not to the trace
-    W = prob.receiver_weights(rl)
-    scale = max(float(np.sum(np.abs(W[r] * want_q[s, 0, re[r]]))) for s in range(S) for r in range(len(re)))
-    assert np.abs(_host(tr) - want_tr).max() < TOL[dtype] * scale
+    # factor of several hundred at N = 9 on this rough initial state), so the
+    # rounding error of each trace is bounded relative to the size of its own
+    # terms, sum_n |W_rn| |p_n| at that step and shot (from the oracle's
+    # state), not relative to the trace; a trace whose terms are all zero
+    # must be zero
+    err = np.abs(_host(tr) - want_tr)
+    bad = np.argwhere(err > TOL[dtype] * scale)
+    assert bad.size == 0, [(tuple(i), err[tuple(i)], scale[tuple(i)]) for i in bad[:5]]
     bs.check()
     bs.close()
 
@@ -161,8 +164,8 @@ def test_source_coefficients_match_oracle():
 
 def test_c4_full_size_sampled():
     """The 64-shot, 24,576-tet, N = 4 FP32 workload in the launch configuration
-    the benchmark times (autotuned), two steps: the last shot (largest
-    offsets) re-run by the oracle, and for every shot the pressure integral,
+    the benchmark times (autotuned), two steps: the first and the last shot
+    (smallest and largest offsets) re-run by the oracle, and for every shot the pressure integral,
     which only the source changes, against the same LSRK quadrature of the
     wavelet."""
     import paper_1512_06025_amd as P
@@ -182,7 +185,7 @@ def test_c4_full_size_sampled():
     prob = dg.Problem(VX, EToV, cfg["N"], c)
     se, sl = prob.locate(src)
     re, rl = prob.locate(rec)
-    for s in (S - 1,):
+    for s in (0, S - 1):
         want, wtr = prob.run_shots(np.zeros((1, 4, prob.K, prob.Np)), dt, steps, se[s:s + 1], sl[s:s + 1],
                                    cfg["f0"], cfg["ts"], re, rl, t0=t0)
         assert _rel(qh[s], want[0]) < 1e-5, s

@@ -57,6 +57,51 @@ def test_rhs_parity(N, dtype):
     s.close()
 
 
+# Every stage-kernel instantiation that bbdg_run can launch: order N, element
+# type, and for FP64 plain or non-temporal output stores (the latter is what
+# meshes whose fields exceed the last-level cache get; forced here on a small
+# mesh).  The instantiations differ in team size (N = 4, 6 and, in FP64,
+# 8 and 9 share an element group between several waves), lift batch size,
+# late residual loads (FP64 N >= 6, FP32 N >= 8) and stores.
+STAGE_CASES = ([(N, "f64", "plain") for N in range(1, 10)] + [(N, "f64", "nontemporal") for N in range(1, 10)]
+               + [(N, "f32", "plain") for N in range(1, 10)])
+
+
+@pytest.mark.parametrize("N,dtype,policy", STAGE_CASES)
+def test_stage_every_instantiation(N, dtype, policy):
+    """One LSRK4 step (five fused stage launches; the first reads no
+    residual) on 155 jittered tets with c ~ U[1,3] and interior boundary
+    faces, every coefficient against the oracle."""
+    P, mesh, c, prob = _setup(3, N, drop_last=7)
+    q = workload.random_coeffs(prob.K, prob.Np, seed=50 + N)
+    if dtype == "f32":
+        q = q.astype(np.float32).astype(np.float64)
+    s = P.Solver(N, mesh, c, dtype=dtype)
+    s.set_store_policy(policy)
+    assert s.nontemporal_stores() == (policy == "nontemporal")
+    qd = _to_dev(q, dtype)
+    dt = 0.4 / (3.0 * 3 * (N + 1) ** 2)
+    s.run(qd, dt, 1)
+    err = _rel(_host(qd), prob.lsrk4(q, dt, 1))
+    assert err < TOL[dtype], (N, dtype, policy, err)
+    s.close()
+
+
+def test_store_policy_arguments():
+    P, mesh, c, prob = _setup(2, 3)
+    s = P.Solver(3, mesh, c, dtype="f64")
+    assert not s.nontemporal_stores()          # 48 tets: auto picks plain stores
+    s.set_store_policy("nontemporal")
+    assert s.nontemporal_stores()
+    from paper_1512_06025_amd import _lib
+    assert _lib.load().bbdg_set_store_policy(s._h, 3) == -1
+    s.close()
+    s32 = P.Solver(3, mesh, c, dtype="f32")
+    s32.set_store_policy("nontemporal")
+    assert not s32.nontemporal_stores()       # FP32 has plain stores only
+    s32.close()
+
+
 @pytest.mark.parametrize("bc", ["rigid", "pressure_release"])
 def test_rhs_parity_boundary_conditions(bc):
     P, mesh, c, prob = _setup(3, 4, bc=bc)
