@@ -1,21 +1,31 @@
 #!/usr/bin/env python3
 """Forward-solver benchmark of the Bernstein-Bezier DG path on one MI355X.
 
-Default workload (the forward-throughput configuration): the unit cube split
+Headline workload (the forward-throughput configuration): the unit cube split
 into 16^3 x 6 = 24,576 affine tets with interior vertices jittered by +-10% of
 h (seeded), order N = 5 (Np = 56), fields p,u,v,w, unit wavespeed, rigid
 walls, standing-mode initial pressure, LSRK4 with dt = 0.5 h/(N+1)^2.
 A bench "step" is one LSRK4 time step = five fused stage kernels (volume +
 surface + update each); inputs are resident in HBM before timing starts.
 
+Timing: W warm-up steps, then more warm-up runs until at least 200 ms of
+wall-clock time has passed, then 5 timed runs of K steps each, every run
+bracketed by torch.cuda.synchronize() and HIP events recorded on the stream
+the kernels run on; the reported time is the median run.
+
 Prints one JSON line: DoF-stage updates/s (4 K Np per stage) for FP64 (the
-headline value), plus the FP32 run on the same workload, the roofline
-placement of the stage kernel, and the FP64 CPU oracle timed on a bounded
-sample on the host cores.
+headline value), the FP32 run on the same workload, the dense nodal
+comparator, the order sweep on 32^3 x 6 = 196,608 tets (the configuration
+whose fields do not fit in the 256 MB last-level cache, where the stage
+kernel's roofline placement is taken), the 64-shot batched workload, the
+misfit gradient, a streaming-copy probe, and the FP64 CPU oracle timed on
+bounded samples on the host cores.
 """
 import argparse
+import gc
 import json
 import os
+import statistics
 import sys
 import time
 
@@ -23,6 +33,9 @@ import numpy as np
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak
 ROOT = os.path.dirname(os.path.abspath(__file__))
+REPS = 5
+MIN_WARM_MS = 200.0
+LEGS = ("c2", "fp32", "nodal", "c3", "batched", "gradient", "copy", "cpu")
 
 
 def recorded_traffic(kernel, workload):
@@ -50,42 +63,122 @@ def recorded_traffic(kernel, workload):
     return None
 
 
-def stage_kernel_name(N, K):
-    """Name of the FP64 stage kernel instantiation the library launches for
-    order N on K elements: waves per workgroup (three at N = 8, else four)
-    and non-temporal output stores when the state, residual and second
-    buffer (3 x 4 K Np doubles) exceed the 256 MB last-level cache."""
-    Np = (N + 1) * (N + 2) * (N + 3) // 6
-    wpb = 3 if N == 8 else 4
-    nt = 3 * 4 * K * Np * 8 > 256 * 1024 * 1024
-    return "bb_stage_kernel<%d, double, 0, %d, %s>" % (N, wpb, "true" if nt else "false")
+def stage_kernel_name(N, dtype, nt):
+    """Name of the stage kernel instantiation the library launches for order
+    N: waves per workgroup (three at N = 8 in FP64, else four) and whether
+    the non-temporal-store variant runs (reported by the library)."""
+    t = "double" if dtype == "f64" else "float"
+    wpb = 3 if (N == 8 and dtype == "f64") else 4
+    return "bb_stage_kernel<%d, %s, 0, %d, %s>" % (N, t, wpb, "true" if nt else "false")
 
 
 def algorithmic_bytes_per_element(N, word):
-    """w (16 Np + 16 Nfp + 14) + 20 bytes: read q and res, read the 4 faces'
-    neighbour traces, write q and res; 14 words of geometry, 20 B of indices."""
+    """Bytes a fused stage must move per element, averaged over the five
+    stages of an LSRK4 step: read q (4 Np words) and the residual (4 Np,
+    skipped by the first stage, whose residual coefficient is zero), read
+    the four faces' neighbour traces (16 Nfp), write q and the residual
+    (8 Np); 14 words of geometry and 20 B of connectivity.
+    = w (16 Np + 16 Nfp + 14) + 20 - w 4 Np / 5."""
     Np = (N + 1) * (N + 2) * (N + 3) // 6
     Nfp = (N + 1) * (N + 2) // 2
-    return word * (16 * Np + 16 * Nfp + 14) + 20
+    return word * (16 * Np + 16 * Nfp + 14) + 20 - word * 4.0 * Np / 5.0
 
 
-def time_gpu(P, torch, N, mesh, c, q0, dt, steps, warmup, dtype, basis="bb"):
+def timed_runs(torch, run, stream):
+    """Wall-clock warm-up of at least MIN_WARM_MS (run() repeated, each
+    followed by a device synchronisation), then REPS timed runs, each
+    bracketed by synchronisations and by HIP events on `stream`.  Returns
+    the list of run times in ms."""
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    while (time.perf_counter() - t0) * 1e3 < MIN_WARM_MS:
+        run()
+        torch.cuda.synchronize()
+    out = []
+    for _ in range(REPS):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        run()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        out.append(e0.elapsed_time(e1))
+    return out
+
+
+def time_solver(P, torch, N, mesh, c, q0, dt, steps, warmup, dtype, basis="bb"):
+    """Median ms of REPS runs of `steps` LSRK4 steps (after W warm-up steps
+    and the wall-clock warm-up); also the run times, whether the state
+    stayed finite, the state after the W warm-up steps plus one timed-size
+    run (for error comparisons), and whether non-temporal stores ran."""
     s = P.Solver(N, mesh, c, dtype=dtype, basis=basis)
     q = torch.from_numpy(q0).to("cuda", s.torch_dtype)
     stream = torch.cuda.current_stream()
     if warmup:
         s.run(q, dt, warmup, stream=stream)
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
     s.run(q, dt, steps, stream=stream)
-    e1.record(stream)
     torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1)
+    q_ref = q.clone()
+    ms = timed_runs(torch, lambda: s.run(q, dt, steps, stream=stream), stream)
     finite = bool(torch.isfinite(q).all().item())
+    nt = basis == "bb" and s.nontemporal_stores()
     s.close()
-    return ms, finite, q
+    del q
+    return statistics.median(ms), ms, finite, q_ref, nt
+
+
+def roofline_obj(N, dtype, K, stage_us, nt, workload_tag, cache_assisted):
+    w = 8 if dtype == "f64" else 4
+    bytes_launch = algorithmic_bytes_per_element(N, w) * K
+    achieved = bytes_launch / (stage_us * 1e-6) / 1e9
+    kern = stage_kernel_name(N, dtype, nt)
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": recorded_traffic(kern, workload_tag),
+            "kernel": kern, "workload": workload_tag, "bytes_per_launch": bytes_launch,
+            "bytes_per_element": algorithmic_bytes_per_element(N, w), "avg_launch_us": stage_us,
+            "cache_assisted": cache_assisted}
+
+
+def time_c3(P, torch, workload, ic, orders, dtypes, steps, nodal_steps, warmup):
+    """Order sweep on 32^3 x 6 = 196,608 tets, c ~ U[1,3], Gaussian pulse:
+    per-stage time and HBM roofline placement of the BB stage for each
+    order and element type, and the dense nodal comparator beside it."""
+    cfg, VX, EToV, c = workload.build_preset("c3")
+    K = cfg["K"]
+    mesh = P.mesh_geometry(VX, EToV)
+    out = {"workload": "unit cube 32^3x6 = %d tets, c~U[1,3] (seeded), Gaussian pulse IC, rigid walls, "
+                       "dt = 0.5 h/(3 (N+1)^2); %d steps per timed run (median of %d), nodal %d"
+                       % (K, steps, REPS, nodal_steps), "K": K, "orders": {}}
+    for N in orders:
+        pre = workload.preset("c3", N=N)
+        dt = pre["dt"]
+        Np = pre["Np"]
+        q0 = ic.initial_state(N, VX, EToV, workload.INITIAL_FIELDS[cfg["ic"]])
+        row = {}
+        for dtype in dtypes:
+            med, runs, ok, _, nt = time_solver(P, torch, N, mesh, c, q0, dt, steps, warmup, dtype)
+            st = med * 1e3 / (5 * steps)
+            r = roofline_obj(N, dtype, K, st, nt, "c3 N=%d %s" % (N, dtype), False)
+            r.update(stage_us_runs=[m * 1e3 / (5 * steps) for m in runs], finite=ok,
+                     dof_stage_per_s=4.0 * K * Np / (st * 1e-6))
+            row[dtype] = r
+        if nodal_steps > 0:
+            x0 = ic.initial_state(N, VX, EToV, workload.INITIAL_FIELDS[cfg["ic"]], basis="nodal")
+            Nfp = (N + 1) * (N + 2) // 2
+            flop = K * (24 * Np * Np + 32 * Np * Nfp)
+            for dtype in dtypes:
+                med, runs, ok, _, _ = time_solver(P, torch, N, mesh, c, x0, dt, nodal_steps, 0, dtype,
+                                                  basis="nodal")
+                st = med * 1e3 / (5 * nodal_steps)
+                peak = 78.6 if dtype == "f64" else 157.3
+                tf = flop / (st * 1e-6) / 1e12
+                row["nodal_" + dtype] = {"stage_us": st, "tflops": tf, "mfma_peak_tflops": peak,
+                                         "mfma_frac": tf / peak, "finite": ok,
+                                         "bb_speedup": st / row[dtype]["avg_launch_us"]}
+        out["orders"][str(N)] = row
+        gc.collect()
+    return out
 
 
 def time_batched(P, torch, workload, steps):
@@ -110,15 +203,18 @@ def time_batched(P, torch, workload, steps):
     e1.record(stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
+    bs.check()
     stages = 5 * steps
     stage_us = ms * 1e3 / stages
     gbs = algorithmic_bytes_per_element(N, 4) * K * S / (stage_us * 1e-6) / 1e9
     finite = bool(torch.isfinite(q).all().item() and torch.isfinite(tr).all().item())
     bs.close()
+    del q
     # the same run in FP64 (untimed) for the FP32 error of the traces
     b64 = P.BatchedSolver(N, mesh, c, S, sources=workload.source_positions(S), receivers=workload.receiver_grid(),
                           f0=cfg["f0"], ts=cfg["ts"], dtype="f64", wpb=4)
     tr64 = b64.run(b64.empty_state(), dt, steps)
+    b64.check()
     err32 = float(torch.linalg.norm(tr.double() - tr64) / torch.linalg.norm(tr64))
     b64.close()
     return {"workload": "%d shots, Ricker f0=%g, %d receivers, unit cube %d^3x6 = %d tets, N=%d, c~U[%g,%g], "
@@ -142,7 +238,7 @@ def time_gradient(P, torch, workload, steps):
     # observations: FP64 forward at m_true
     obs_run = P.BatchedSolver(N, mesh, np.sqrt(m_true), S, sources=src, receivers=rec, f0=cfg["f0"], ts=cfg["ts"],
                               dtype="f64", wpb=4)
-    d_obs = obs_run.run(obs_run.empty_state(), dt, steps)
+    d_obs = obs_run.run(obs_run.empty_state(), dt, steps).clone()
     obs_run.close()
     mf = P.Misfit(N, mesh, np.ones(K), S, src, rec, d_obs, dt, steps, f0=cfg["f0"], ts=cfg["ts"],
                   ckpt_every=cfg["ckpt_every"], dtype="f32")
@@ -157,16 +253,22 @@ def time_gradient(P, torch, workload, steps):
     g = mf.gradient()
     ev[2].record(stream)
     torch.cuda.synchronize()
+    mf.check()
     t_fwd, t_adj = ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2])
     finite = bool(torch.isfinite(g).all().item())
     g = g.clone()
     mf.close()
+    del mf
+    gc.collect()
     # the same gradient with FP64 states (untimed) for the FP32 error
     m64 = P.Misfit(N, mesh, np.ones(K), S, src, rec, d_obs, dt, steps, f0=cfg["f0"], ts=cfg["ts"],
                    ckpt_every=cfg["ckpt_every"], dtype="f64")
     J64 = float(m64.evaluate().item())
     g64 = m64.gradient()
+    m64.check()
     m64.close()
+    del m64
+    gc.collect()
     out = {"workload": "misfit gradient dJ/dm, %d shots (Ricker f0=%g on z=0.9), 64 receivers, %d^3x6 = %d tets, "
                        "N=%d, FP32 states / FP64 sums, %d steps, checkpoints every %d" % (
                            S, cfg["f0"], cfg["n"], K, N, steps, cfg["ckpt_every"]),
@@ -177,7 +279,7 @@ def time_gradient(P, torch, workload, steps):
     return out
 
 
-def copy_probe(torch, P, nbytes=1 << 30, reps=20):
+def copy_probe(torch, nbytes=1 << 30, reps=20):
     """Bandwidth of a plain streaming copy (read + write bytes per second)."""
     from paper_1512_06025_amd import _lib
     lib = _lib.load()
@@ -196,26 +298,84 @@ def copy_probe(torch, P, nbytes=1 << 30, reps=20):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / reps
     ok = bool(torch.equal(src, dst))
+    del src, dst
     return {"bytes_moved": 2 * nbytes, "us": ms * 1e3, "GBs": 2 * nbytes / (ms * 1e-3) / 1e9, "ok": ok}
 
 
-def cpu_baseline(VX, EToV, c, N, q0, dt, sample_steps):
-    from threadpoolctl import threadpool_info
+def host_description():
+    cpu = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    cpu = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": len(os.sched_getaffinity(0)), "os_cpu_count": os.cpu_count(), "cpu": cpu}
+
+
+def cpu_baseline(workload, ic_c2, gpu_stage_us):
+    """The FP64 oracle (NumPy, dense operators) timed on the host cores on
+    bounded samples: one LSRK4 step of the headline workload with all BLAS
+    threads (the reported value) and one of its stages on a single thread;
+    the whole 10-step run of the 384-tet N = 3 workload; one stage of the
+    196,608-tet order sweep for N = 1, 3, 5.  Per-stage times beside the
+    GPU's.  The oracle is test infrastructure: this is a reported baseline,
+    not a fallback."""
+    from threadpoolctl import threadpool_info, threadpool_limits
 
     from oracle import dg
-    prob = dg.Problem(VX, EToV, N, c)
-    t0 = time.perf_counter()
-    prob.lsrk4(q0, dt, sample_steps)
-    sec = time.perf_counter() - t0
     threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    per_stage = {}
+    # headline workload: one LSRK4 step (5 stages), all threads
+    cfg, VX, EToV, c = workload.build_preset("c2")
+    prob = dg.Problem(VX, EToV, cfg["N"], c)
     K, Np = prob.K, prob.Np
+    if ic_c2 is None:
+        ic_c2 = dg.initial_state(prob, workload.standing_mode_p0)
+    t0 = time.perf_counter()
+    q = prob.lsrk4(ic_c2, cfg["dt"], 1)
+    sec = time.perf_counter() - t0
+    per_stage["c2"] = sec / 5
+    # the same workload, one stage on one thread
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        r = prob.rhs(q)
+        q = q + cfg["dt"] * r
+        per_stage_1t = time.perf_counter() - t0
+    del prob, q, r
+    # 384 tets, N = 3: the whole 10-step run
+    cfg1, VX1, EToV1, c1 = workload.build_preset("c1")
+    p1 = dg.Problem(VX1, EToV1, cfg1["N"], c1)
+    q1 = dg.initial_state(p1, workload.standing_mode_p0)
+    t0 = time.perf_counter()
+    p1.lsrk4(q1, cfg1["dt"], cfg1["steps"])
+    per_stage["c1"] = (time.perf_counter() - t0) / (5 * cfg1["steps"])
+    # order sweep mesh, N = 1, 3, 5: one stage (right-hand side + update) each
+    cfg3, VX3, EToV3, c3 = workload.build_preset("c3")
+    for N in (1, 3, 5):
+        p3 = dg.Problem(VX3, EToV3, N, c3)
+        q3 = workload.random_coeffs(p3.K, p3.Np, seed=90 + N)
+        t0 = time.perf_counter()
+        r3 = p3.rhs(q3)
+        q3 = q3 + workload.preset("c3", N=N)["dt"] * r3
+        per_stage["c3_N%d" % N] = time.perf_counter() - t0
+        del p3, q3, r3
+        gc.collect()
     return {
-        "value": 4.0 * K * Np * 5 * sample_steps / sec,
+        "value": 4.0 * K * Np / per_stage["c2"],
         "unit": "DoF-stage/s",
         "cores": int(threads),
         "kind": "oracle",
-        "sample": "%d LSRK4 step(s) = %d stages of the FP64 dense-operator oracle on the full "
-                  "K=%d, N=%d mesh (%.1f s)" % (sample_steps, 5 * sample_steps, K, N, sec),
+        "sample": "FP64 dense-operator NumPy oracle: 1 LSRK4 step (5 stages) of the headline workload "
+                  "(K=%d, N=%d) with %d BLAS threads (NumPy's elementwise and einsum parts run on one "
+                  "thread) = value; plus one single-thread stage of the same workload, the whole 10-step "
+                  "384-tet N=3 run, and one stage of the 196,608-tet mesh for N=1,3,5" % (K, cfg["N"], threads),
+        "host": host_description(),
+        "single_thread_value": 4.0 * K * Np / per_stage_1t,
+        "oracle_stage_s": per_stage,
+        "gpu_stage_s": gpu_stage_us,
     }
 
 
@@ -224,19 +384,21 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--config", default="c2", help="named workload (c1..c3)")
-    ap.add_argument("--order", type=int, default=None, help="override N")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-steps", type=int, default=1)
-    ap.add_argument("--no-fp32", action="store_true")
-    ap.add_argument("--no-nodal", action="store_true", help="skip the dense nodal comparator")
-    ap.add_argument("--no-batched", action="store_true", help="skip the 64-shot batched workload")
+    ap.add_argument("--config", default="c2", help="named workload of the headline leg (c1..c3)")
+    ap.add_argument("--order", type=int, default=None, help="override N of the headline leg")
+    ap.add_argument("--legs", default=",".join(LEGS),
+                    help="comma-separated subset of %s" % ",".join(LEGS))
+    ap.add_argument("--c3-orders", default="5,7,9")
+    ap.add_argument("--c3-dtypes", default="f64,f32")
+    ap.add_argument("--c3-steps", type=int, default=40, help="LSRK4 steps per timed run of the order sweep")
+    ap.add_argument("--c3-nodal-steps", type=int, default=2, help="0 skips the nodal comparator on the sweep")
     ap.add_argument("--batched-steps", type=int, default=500)
-    ap.add_argument("--no-gradient", action="store_true", help="skip the misfit-gradient workload")
     ap.add_argument("--gradient-steps", type=int, default=500)
-    ap.add_argument("--no-copy-probe", action="store_true")
     ap.add_argument("--copy-probe-only", action="store_true",
                     help="only run the streaming-copy probe (counter calibration)")
+    for leg in LEGS:
+        ap.add_argument("--no-" + ("cpu-baseline" if leg == "cpu" else "copy-probe" if leg == "copy" else leg),
+                        dest="skip_" + leg, action="store_true")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -244,6 +406,7 @@ def main():
         print("bench.py: this solver runs on a single GPU; multi-GPU runs (--gpus %d) are not "
               "supported by this build" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    legs = set(x for x in args.legs.split(",") if x) - set(l for l in LEGS if getattr(args, "skip_" + l))
 
     import torch
 
@@ -252,7 +415,7 @@ def main():
     from paper_1512_06025_amd import ic
 
     if args.copy_probe_only:
-        print(json.dumps({"copy_probe": copy_probe(torch, P)}), flush=True)
+        print(json.dumps({"copy_probe": copy_probe(torch)}), flush=True)
         return
 
     over = {} if args.order is None else {"N": args.order}
@@ -264,20 +427,14 @@ def main():
 
     stages = 5 * args.steps
     dof = 4.0 * K * Np
-    ms64, ok64, q64 = time_gpu(P, torch, N, mesh, c, q0, dt, args.steps, args.warmup, "f64")
-    value = dof * stages / (ms64 * 1e-3)
-    stage_us = ms64 * 1e3 / stages
-    bytes_launch = algorithmic_bytes_per_element(N, 8) * K
-    achieved = bytes_launch / (stage_us * 1e-6) / 1e9
-
     out = {
         "metric": "DoF-stage updates/s & % HBM roofline (BB vs nodal, FP64/FP32); grad/forward x",
-        "value": value,
+        "value": None,
         "unit": "DoF-stage/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms64 / args.steps,
+        "ms_per_step": None,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -285,58 +442,97 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": "BB-DG acoustic forward, unit cube %d^3x6 = %d tets%s, N=%d (Np=%d), %s IC, "
-                        "rigid walls, LSRK4 dt=%.6g, %d steps" % (
+                        "rigid walls, LSRK4 dt=%.6g, %d steps per timed run" % (
                             cfg["n"], K, ", interior vertices jittered +-%g h" % cfg["jitter"] if cfg["jitter"] else "",
                             N, Np, cfg["ic"], dt, args.steps),
             "K": K, "N": N, "Np": Np, "Nfp": Nfp, "stages": stages,
             "parallelism": "single GPU",
         },
-        "stage_us": stage_us,
-        "finite": ok64,
-        "roofline": {
-            "bound": "hbm",
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": recorded_traffic(stage_kernel_name(N, K), args.config),
-            "kernel": stage_kernel_name(N, K),
-            "bytes_per_launch": bytes_launch,
-            "avg_launch_us": stage_us,
-        },
+        "timing": "W warm-up steps, >= %g ms wall-clock warm-up, then the median of %d timed runs of K steps "
+                  "(HIP events on the kernels' stream, device synchronised around each run)" % (MIN_WARM_MS, REPS),
     }
-    if not args.no_fp32:
-        ms32, ok32, q32 = time_gpu(P, torch, N, mesh, c, q0, dt, args.steps, args.warmup, "f32")
+    gpu_stage_s = {}
+    q64 = None
+    ms64 = None
+    if "c2" in legs:
+        ms64, runs64, ok64, q64, nt64 = time_solver(P, torch, N, mesh, c, q0, dt, args.steps, args.warmup, "f64")
+        stage_us = ms64 * 1e3 / stages
+        out["value"] = dof * stages / (ms64 * 1e-3)
+        out["ms_per_step"] = ms64 / args.steps
+        out["ms_per_step_runs"] = [m / args.steps for m in runs64]
+        out["stage_us"] = stage_us
+        out["finite"] = ok64
+        gpu_stage_s[args.config] = stage_us * 1e-6
+        # at 24,576 tets the fields (88 MB per copy) fit in the 256 MB last-level cache
+        out["c2_roofline"] = roofline_obj(N, "f64", K, stage_us, nt64, args.config,
+                                          cache_assisted=bool(K * Np * 4 * 8 * 3 <= 256 * 1024 * 1024))
+    if "fp32" in legs:
+        ms32, runs32, ok32, q32, _ = time_solver(P, torch, N, mesh, c, q0, dt, args.steps, args.warmup, "f32")
         st32 = ms32 * 1e3 / stages
         a32 = algorithmic_bytes_per_element(N, 4) * K / (st32 * 1e-6) / 1e9
-        # both runs did warm-up + steps steps from q0; the FP64 path matches the oracle to 1e-12
-        err32 = float(torch.linalg.norm(q32.double() - q64) / torch.linalg.norm(q64))
-        out["fp32"] = {"value": dof * stages / (ms32 * 1e-3), "ms_per_step": ms32 / args.steps,
-                       "stage_us": st32, "achieved_GBs": a32, "frac": a32 / HBM_PEAK_GBS, "finite": ok32,
-                       "rel_l2_error_vs_fp64": err32}
-    if not args.no_nodal:
+        f32 = {"value": dof * stages / (ms32 * 1e-3), "ms_per_step": ms32 / args.steps,
+               "stage_us": st32, "achieved_GBs": a32, "frac": a32 / HBM_PEAK_GBS, "finite": ok32}
+        if q64 is not None:
+            # both runs took the same W + K steps from q0 before the copy;
+            # the FP64 path matches the oracle to 1e-12
+            f32["rel_l2_error_vs_fp64"] = float(torch.linalg.norm(q32.double() - q64) / torch.linalg.norm(q64))
+        out["fp32"] = f32
+        del q32
+    if "nodal" in legs:
         x0 = ic.initial_state(N, VX, EToV, workload.INITIAL_FIELDS[cfg["ic"]], basis="nodal")
         nod = {}
-        for dt_name, bb_ms in (("f64", ms64), ("f32", out.get("fp32", {}).get("ms_per_step", 0) * args.steps)):
-            if dt_name == "f32" and args.no_fp32:
-                continue
-            msn, okn, _ = time_gpu(P, torch, N, mesh, c, x0, dt, args.steps, args.warmup, dt_name, basis="nodal")
+        for dtn in ("f64", "f32"):
+            msn, runsn, okn, _, _ = time_solver(P, torch, N, mesh, c, x0, dt, args.steps, args.warmup, dtn,
+                                                basis="nodal")
             flop = K * (24 * Np * Np + 32 * Np * Nfp)  # dense volume + lift per stage
-            nod[dt_name] = {"value": dof * stages / (msn * 1e-3), "stage_us": msn * 1e3 / stages,
-                            "tflops": flop * stages / (msn * 1e-3) / 1e12, "finite": okn,
-                            "bb_speedup": msn / bb_ms}
+            peak = 78.6 if dtn == "f64" else 157.3
+            tf = flop * stages / (msn * 1e-3) / 1e12
+            e = {"value": dof * stages / (msn * 1e-3), "stage_us": msn * 1e3 / stages, "tflops": tf,
+                 "mfma_frac": tf / peak, "finite": okn}
+            bb = ms64 if dtn == "f64" else out.get("fp32", {}).get("ms_per_step", 0) * args.steps
+            if bb:
+                e["bb_speedup"] = msn / bb
+            nod[dtn] = e
         out["nodal"] = nod
-    if not args.no_batched:
+    del q64
+    if "c3" in legs:
+        orders = [int(x) for x in args.c3_orders.split(",") if x]
+        dtypes = [x for x in args.c3_dtypes.split(",") if x]
+        c3 = time_c3(P, torch, workload, ic, orders, dtypes, args.c3_steps, args.c3_nodal_steps, args.warmup)
+        out["c3"] = c3
+        for Nk, row in c3["orders"].items():
+            if "f64" in row:
+                gpu_stage_s["c3_N%s" % Nk] = row["f64"]["avg_launch_us"] * 1e-6
+        head = c3["orders"].get("5", c3["orders"].get(str(orders[0]), {}))
+        if "f64" in head:
+            out["roofline"] = head["f64"]
+    if "roofline" not in out and "c2_roofline" in out:
+        out["roofline"] = out["c2_roofline"]
+    if "batched" in legs:
         out["batched"] = time_batched(P, torch, workload, args.batched_steps)
-    if not args.no_gradient:
+    if "gradient" in legs:
         out["gradient"] = time_gradient(P, torch, workload, args.gradient_steps)
-    if not args.no_copy_probe:
-        cp = copy_probe(torch, P)
-        out["roofline"]["copy_probe_GBs"] = cp["GBs"]
-        out["roofline"]["frac_of_copy_probe"] = achieved / cp["GBs"]
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(VX, EToV, c, N, q0, dt, args.cpu_sample_steps)
+    if "copy" in legs:
+        cp = copy_probe(torch)
+        for key in ("roofline", "c2_roofline"):
+            if key in out:
+                out[key]["copy_probe_GBs"] = cp["GBs"]
+                out[key]["frac_of_copy_probe"] = out[key]["achieved"] / cp["GBs"]
+    # every device buffer is released before the host-only baseline and the exit
+    gc.collect()
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    if "cpu" in legs:
+        if "c1" not in gpu_stage_s and "c2" in legs:
+            cfg1, VX1, EToV1, c1 = workload.build_preset("c1")
+            x1 = ic.initial_state(cfg1["N"], VX1, EToV1, workload.INITIAL_FIELDS[cfg1["ic"]])
+            m1, _, _, _, _ = time_solver(P, torch, cfg1["N"], P.mesh_geometry(VX1, EToV1), c1, x1, cfg1["dt"],
+                                         cfg1["steps"], 0, "f64")
+            gpu_stage_s["c1"] = m1 * 1e-3 / (5 * cfg1["steps"])
+        headline_is_c2 = args.config == "c2" and args.order is None
+        out["cpu_baseline"] = cpu_baseline(workload, q0 if headline_is_c2 else None, gpu_stage_s)
     print(json.dumps(out), flush=True)
+    torch.cuda.synchronize()
 
 
 if __name__ == "__main__":

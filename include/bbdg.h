@@ -261,6 +261,22 @@ int bbdg_run_batched(bbdg_solver* s, void* q, int64_t shots, const int32_t* src_
  * overwritten.  Synchronises the device. */
 int bbdg_tune_batched(bbdg_solver* s, int64_t shots, void* scratch, int* wpb, void* stream);
 
+/* Co-residency of the persistent batched kernel for this handle's order and
+ * element type with wpb (2, 4, 8) waves per workgroup; record != 0 asks for
+ * the instantiation that also records stages for the misfit gradient.
+ * out (host, 6 int32): workgroups per CU that the runtime's occupancy query
+ * reports; the bound derived from the kernel's own resources, which the
+ * cooperative launches use (VGPRs: 512 per SIMD lane in granules of 8, at
+ * most 8 waves per SIMD, two-wave workgroups counted as sharing two SIMDs;
+ * LDS: 160 KiB per CU in 2 KiB granules; 0 for a kernel that uses scratch
+ * memory; at most 8 and at most the query's count); VGPRs per lane; static
+ * LDS bytes per workgroup; scratch bytes per lane; CUs of the device.
+ * A shape whose bound is 0 is refused by bbdg_run_batched (BBDG_E_RESIDENT)
+ * and skipped by bbdg_tune_batched; the misfit calls use the tuned shape when
+ * both of its instantiations have a bound of at least 1, else the first of
+ * 4, 2, 8 that has (BBDG_E_RESIDENT if none). */
+int bbdg_batched_occupancy(const bbdg_solver* s, int wpb, int record, int32_t* out);
+
 /* ---- Receiver misfit and its gradient ---------------------------------------
  * For the batched forward run above (shots, sources, receivers, t0, dt,
  * steps) with traces d (steps x shots x R) and observations d_obs of the same

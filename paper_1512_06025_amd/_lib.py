@@ -55,6 +55,7 @@ SIGNATURES = {
                                     _c.c_void_p, _c.c_void_p, _c.c_double, _c.c_double, _c.c_int64,
                                     _c.c_int, _c.c_void_p]),
     "bbdg_status": (_c.c_int, [_c.c_void_p]),
+    "bbdg_batched_occupancy": (_c.c_int, [_c.c_void_p, _c.c_int, _c.c_int, _c.c_void_p]),
     "bbdg_set_barrier_timeout": (_c.c_int, [_c.c_void_p, _c.c_double]),
     "bbdg_tune_batched": (_c.c_int, [_c.c_void_p, _c.c_int64, _c.c_void_p, _c.POINTER(_c.c_int),
                                      _c.c_void_p]),

@@ -59,6 +59,14 @@ hipError_t launch_stage(int N, int mode, const StageArgs<T>& a, hipStream_t stre
 template <typename T>
 hipError_t launch_batched(int N, int wpb, const StageArgs<T>& a, hipStream_t stream);
 
+// Co-residency of the batched kernel of order N with wpb waves per workgroup
+// (record != 0: the instantiation that records stages for the adjoint) on
+// the current device: out = {workgroups per CU by the occupancy query, the
+// bound derived from the kernel's VGPRs, LDS and scratch (what cooperative
+// launches use), VGPRs, static LDS bytes, scratch bytes per lane, CUs}.
+template <typename T>
+hipError_t batched_residency(int N, int wpb, int record, int out[6]);
+
 // Zeroes the arrival counters of the grid barrier (one tiny kernel).
 hipError_t launch_barrier_reset(uint32_t* sync, hipStream_t stream);
 

@@ -127,15 +127,24 @@ __device__ __forceinline__ void team_sync() {
 }
 
 // Occupancy target (waves per SIMD) that bounds the register allocation.
-template <int N, typename T, int TW, bool BATCH>
+template <int N, typename T, int TW, int MODE, int WPB>
 struct Occ {
+  static constexpr bool kB = MODE >= kBatched;
+  static constexpr bool kD = sizeof(T) == 8;
   static constexpr int f64[10] = {0, 2, 3, 4, 4, 4, 3, 3, 2, 2};
   static constexpr int f32[10] = {0, 3, 4, 5, 5, 5, 5, 4, 4, 3};
   // the batched kernel carries more stage state (buffers, coefficients, source)
   static constexpr int f64b[10] = {0, 2, 3, 4, 4, 4, 3, 3, 2, 2};
   static constexpr int f32b[10] = {0, 3, 4, 5, 5, 6, 4, 4, 3, 3};
-  static constexpr int value =
-      TW > 1 ? 4 : (sizeof(T) == 8 ? (BATCH ? f64b[N] : f64[N]) : (BATCH ? f32b[N] : f32[N]));
+  static constexpr int base = TW > 1 ? 4 : (kD ? (kB ? f64b[N] : f64[N]) : (kB ? f32b[N] : f32[N]));
+  // batched shapes whose registers do not fit the base target (the compiler
+  // spilled them to scratch memory) get one level less; a kernel that uses
+  // scratch memory is not launched cooperatively (see kernel_residency)
+  static constexpr bool kLess =
+      kB && ((kD && N == 3 && WPB == 8) || (kD && N == 4 && WPB == 4 && MODE == kBatchedRecord) ||
+             (kD && N == 6 && (WPB == 4 || (WPB == 8 && MODE == kBatchedRecord))) ||
+             (!kD && N == 5 && MODE == kBatchedRecord) || (!kD && N == 9 && WPB == 4 && MODE == kBatchedRecord));
+  static constexpr int value = kLess ? base - 1 : base;
 };
 
 template <int N>
@@ -277,7 +286,7 @@ constexpr int team_waves() {
 }
 
 template <int N, typename T, int MODE, int WPB, bool NT = false>
-__global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(Occ<N, T, team_waves<N, T, MODE, WPB>(), MODE >= kBatched>::value)))
+__global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(Occ<N, T, team_waves<N, T, MODE, WPB>(), MODE, WPB>::value)))
 void bb_stage_kernel(StageArgs<T> A) {
   using S = Shape<N, T>;
   constexpr bool kBatch = (MODE == kBatched || MODE == kBatchedRecord);
@@ -826,25 +835,67 @@ hipError_t launch_poison(const uint32_t* sync, T* a, int64_t n, hipStream_t stre
 template hipError_t launch_poison<double>(const uint32_t*, double*, int64_t, hipStream_t);
 template hipError_t launch_poison<float>(const uint32_t*, float*, int64_t, hipStream_t);
 
+// Workgroups of a kernel that one CU holds at a time.  `api` is what the
+// runtime's occupancy query reports; `bound` is derived here from the
+// kernel's own resources, so that a cooperative grid never relies on the
+// query alone:
+//   VGPRs: 512 per SIMD lane, allocated in granules of 8, at most 8 waves per
+//     SIMD; a workgroup of 4 or 8 waves puts the same number of waves on each
+//     of the CU's 4 SIMDs; a two-wave workgroup is counted as if every such
+//     workgroup used the same two SIMDs (the placement is not documented);
+//   LDS: 160 KiB per CU, a workgroup's static LDS rounded up to 2 KiB;
+//   scratch memory: a kernel that uses any is not proven co-resident (its
+//     waves also need scratch space that the runtime sizes), bound 0;
+//   at most 8 workgroups per CU for the persistent grids.
+// The bound is min(api, the above).
+struct Residency {
+  int api = 0, bound = 0, vgprs = 0, lds = 0, scratch = 0, cus = 0;
+  hipError_t err = hipSuccess;
+};
+
+template <int N, typename T, int MODE, int WPB, bool NT = false>
+static const Residency& kernel_residency() {
+  static Residency r;
+  static bool done = false;
+  if (done) return r;
+  const void* fn = reinterpret_cast<const void*>(bb_stage_kernel<N, T, MODE, WPB, NT>);
+  int dev = 0;
+  r.err = hipGetDevice(&dev);
+  if (r.err == hipSuccess) r.err = hipDeviceGetAttribute(&r.cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (r.err == hipSuccess)
+    r.err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&r.api, bb_stage_kernel<N, T, MODE, WPB, NT>, 64 * WPB, 0);
+  hipFuncAttributes fa{};
+  if (r.err == hipSuccess) r.err = hipFuncGetAttributes(&fa, fn);
+  if (r.err != hipSuccess) return r;  // not cached: the next call asks again
+  r.vgprs = fa.numRegs;
+  r.lds = (int)fa.sharedSizeBytes;
+  r.scratch = (int)fa.localSizeBytes;
+  int bound = 0;
+  if (r.vgprs > 0 && r.scratch == 0) {
+    const int per_simd = std::min(8, 512 / (((r.vgprs + 7) / 8) * 8));
+    const int by_vgpr = WPB >= 4 ? per_simd * 4 / WPB : per_simd;
+    const int by_lds = r.lds > 0 ? (160 * 1024) / (((r.lds + 2047) / 2048) * 2048) : 8;
+    bound = std::min(std::min(by_vgpr, by_lds), std::min(8, r.api));
+  }
+  r.bound = std::max(bound, 0);
+  done = true;
+  return r;
+}
+
+// Grid of a persistent launch over `groups` element groups, `per_wg` groups
+// per workgroup and pass: the co-resident workgroups, at most what has work,
+// a multiple of 8 (one share per XCD).  Single-stage launches take the
+// occupancy query's count (they need no co-residency: nothing waits across
+// workgroups); cooperative (batched) launches take the derived bound and are
+// refused when it is zero or the grid would fall below 8.
 template <int N, typename T, int MODE, int WPB, bool NT = false>
 static hipError_t resident_grid(int64_t groups, int per_wg, int64_t* grid_out) {
-  static int resident = 0;  // co-resident workgroups per CU for this instantiation
-  static int cus = 0;
-  if (resident == 0) {
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return hipErrorInvalidDevice;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return hipErrorInvalidDevice;
-    int occ = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, bb_stage_kernel<N, T, MODE, WPB, NT>, 64 * WPB, 0) !=
-        hipSuccess)
-      return hipErrorInvalidValue;
-    if (occ < 1) return hipErrorInvalidConfiguration;
-    // persistent cooperative grids stay well inside the per-CU workgroup limit
-    if (MODE >= kBatched && occ > 8) occ = 8;
-    resident = occ;
-  }
+  const Residency& r = kernel_residency<N, T, MODE, WPB, NT>();
+  if (r.err != hipSuccess) return r.err;
+  const int per_cu = MODE >= kBatched ? r.bound : r.api;
+  if (per_cu < 1) return MODE >= kBatched ? hipErrorCooperativeLaunchTooLarge : hipErrorInvalidConfiguration;
   const int64_t needed = (groups + per_wg - 1) / per_wg;  // workgroups with work
-  int64_t grid = (int64_t)resident * cus;
+  int64_t grid = (int64_t)per_cu * r.cus;
   if (grid > ((needed + 7) / 8) * 8) grid = ((needed + 7) / 8) * 8;
   if (MODE >= kBatched) grid = grid / 8 * 8;  // stay within the co-resident bound
   else grid = ((grid + 7) / 8) * 8;
@@ -928,6 +979,44 @@ hipError_t launch_batched(int N, int wpb, const StageArgs<T>& a, hipStream_t str
 
 template hipError_t launch_batched<double>(int, int, const StageArgs<double>&, hipStream_t);
 template hipError_t launch_batched<float>(int, int, const StageArgs<float>&, hipStream_t);
+
+template <int N, typename T, int WPB>
+static hipError_t residency_of(int record, int out[6]) {
+  const Residency& r = record ? kernel_residency<N, T, kBatchedRecord, WPB>() : kernel_residency<N, T, kBatched, WPB>();
+  out[0] = r.api;
+  out[1] = r.bound;
+  out[2] = r.vgprs;
+  out[3] = r.lds;
+  out[4] = r.scratch;
+  out[5] = r.cus;
+  return r.err;
+}
+
+template <typename T>
+hipError_t batched_residency(int N, int wpb, int record, int out[6]) {
+#define BBDG_RES_CASE(NN)                                          \
+  case NN:                                                         \
+    if (wpb == 2) return residency_of<NN, T, 2>(record, out);      \
+    if (wpb == 4) return residency_of<NN, T, 4>(record, out);      \
+    if (wpb == 8) return residency_of<NN, T, 8>(record, out);      \
+    return hipErrorInvalidValue;
+  switch (N) {
+    BBDG_RES_CASE(1)
+    BBDG_RES_CASE(2)
+    BBDG_RES_CASE(3)
+    BBDG_RES_CASE(4)
+    BBDG_RES_CASE(5)
+    BBDG_RES_CASE(6)
+    BBDG_RES_CASE(7)
+    BBDG_RES_CASE(8)
+    BBDG_RES_CASE(9)
+    default: return hipErrorInvalidValue;
+  }
+#undef BBDG_RES_CASE
+}
+
+template hipError_t batched_residency<double>(int, int, int, int[6]);
+template hipError_t batched_residency<float>(int, int, int, int[6]);
 
 template <typename T, int MODE>
 static hipError_t launch_mode(int N, const StageArgs<T>& a, hipStream_t stream) {

@@ -568,6 +568,25 @@ bool batched_shape_ok(const bbdg_solver* s, int64_t shots) {
   return shots <= ((int64_t)1 << 32) / G - 1;
 }
 
+// Waves per workgroup of the misfit runs: the tuned shape when both its
+// plain and its recording instantiation can be co-resident, else the first
+// of 4, 2, 8 that can (0: none).
+int misfit_wpb(const bbdg_solver* s, int64_t shots) {
+  auto ok = [&](int w) {
+    for (int rec = 0; rec < 2; ++rec) {
+      int o[6] = {0, 0, 0, 0, 0, 0};
+      const hipError_t e = s->dtype == BBDG_F64 ? batched_residency<double>(s->N, w, rec, o)
+                                                : batched_residency<float>(s->N, w, rec, o);
+      if (e != hipSuccess || o[1] < 1) return false;
+    }
+    return true;
+  };
+  if (s->tuned_shots == shots && s->tuned_wpb && ok(s->tuned_wpb)) return s->tuned_wpb;
+  for (int w : {4, 2, 8})
+    if (ok(w)) return w;
+  return 0;
+}
+
 // Work-space layout of the misfit and its gradient (offsets in bytes, each
 // part 256-byte aligned).
 struct GradLayout {
@@ -621,7 +640,8 @@ int misfit_typed(bbdg_solver* s, int64_t shots, const T* q0, const int32_t* src_
   T* fwork = (T*)(work + L.fwork);
   T* ckpt = (T*)(work + L.ckpt);
   T* traces = (T*)(work + L.traces);
-  const int wpb = (s->tuned_shots == shots && s->tuned_wpb) ? s->tuned_wpb : 4;
+  const int wpb = misfit_wpb(s, shots);
+  if (wpb == 0) return BBDG_E_RESIDENT;
   double* amp = (double*)(work + L.amp);  // wavelet at every stage of the run
   T* rec_p = (T*)(work + L.rec_p);
   T* rec_j = (T*)(work + L.rec_j);
@@ -1208,6 +1228,17 @@ int bbdg_tune_batched(bbdg_solver* s, int64_t shots, void* scratch, int* wpb, vo
   s->tuned_shots = shots;
   s->tuned_wpb = best;
   *wpb = best;
+  return BBDG_OK;
+}
+
+int bbdg_batched_occupancy(const bbdg_solver* s, int wpb, int record, int32_t* out) {
+  if (!s || !out || s->basis != 0 || (wpb != 2 && wpb != 4 && wpb != 8)) return BBDG_E_ARG;
+  if (hipSetDevice(s->device) != hipSuccess) return BBDG_E_DEVICE;
+  int o[6] = {0, 0, 0, 0, 0, 0};
+  const hipError_t e = s->dtype == BBDG_F64 ? batched_residency<double>(s->N, wpb, record ? 1 : 0, o)
+                                            : batched_residency<float>(s->N, wpb, record ? 1 : 0, o);
+  if (e != hipSuccess) return hip_fail(e, BBDG_E_DEVICE);
+  for (int i = 0; i < 6; ++i) out[i] = o[i];
   return BBDG_OK;
 }
 

@@ -208,3 +208,36 @@ def test_c4_full_size_sampled():
         scale = np.sum(np.abs(prob.geo.volume[:, None] * qh[s][0] * msum[None, :] / prob.kappa[:, None]))
         assert abs(got - I) < 1e-5 * scale, (s, got, I, scale)
     bs.close()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_residency_bound(dtype):
+    """For every order and batched launch shape, the co-residency bound that
+    cooperative launches use never exceeds the occupancy query, is zero for
+    a kernel that uses scratch memory and at least one otherwise; a shape
+    with bound zero is refused before anything runs."""
+    import ctypes
+
+    import paper_1512_06025_amd as P
+    from paper_1512_06025_amd import _lib
+    lib = _lib.load()
+    VX, EToV = workload.kuhn_cube_mesh(2, 0.0)
+    mesh = P.mesh_geometry(VX, EToV)
+    for N in range(1, 10):
+        s = P.Solver(N, mesh, 1.0, dtype=dtype)
+        for wpb in (2, 4, 8):
+            for record in (0, 1):
+                out = (ctypes.c_int32 * 6)()
+                _lib.check(lib.bbdg_batched_occupancy(s._h, wpb, record, out), "bbdg_batched_occupancy")
+                api, bound, vgprs, lds, scratch, cus = list(out)
+                assert cus > 0 and vgprs > 0 and api >= 1, (N, wpb, record, list(out))
+                assert 0 <= bound <= min(api, 8), (N, wpb, record, list(out))
+                assert (bound == 0) == (scratch > 0), (N, wpb, record, list(out))
+                assert lds <= 160 * 1024
+                if record == 0 and bound == 0:
+                    bs = P.BatchedSolver(N, mesh, 1.0, 1, dtype=dtype, wpb=wpb)
+                    with pytest.raises(P.BBDGError) as err:
+                        bs.run(bs.empty_state(), 1e-3, 1)
+                    assert err.value.code == -11
+                    bs.close()
+        s.close()
