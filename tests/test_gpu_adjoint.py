@@ -43,6 +43,22 @@ def _oracle(VX, EToV, m, src, rec, obs, N, bc="rigid", dt=2e-3, t0=0.08):
     return A.gradient(q0, dt, obs.shape[0], se, sl, F0, TS, re, rl, obs, t0)
 
 
+def _J_bar(VX, EToV, m, src, rec, obs, N, bc="rigid", dt=2e-3, t0=0.08, tol=1e-12):
+    """Rounding bound of J = 1/2 sum r^2, r = d - d_obs: each trace d is a
+    dot product of receiver weights and coefficients whose error is bounded
+    by tol * sum_n |W_rn| |p_n| (its own terms, which cancel by up to a few
+    hundred at N = 9), so |dJ| <= tol * sum |r| sum_n |W_rn| |p_n|, plus the
+    summation of J itself."""
+    A = adjoint.Adjoint(VX, EToV, N, m, bc)
+    p = A.prob
+    se, sl = p.locate(src)
+    re, rl = p.locate(rec)
+    q0 = np.zeros((src.shape[0], 4, p.K, p.Np))
+    _, tr, sc = p.run_shots(q0, dt, obs.shape[0], se, sl, F0, TS, re, rl, t0, trace_scales=True)
+    r = tr - obs
+    return tol * float(np.sum(np.abs(r) * sc)) + 1e-13 * 0.5 * float(np.sum(r ** 2))
+
+
 @pytest.mark.parametrize("N,ckpt,bc", [(1, 0, "rigid"), (2, 0, "rigid"), (3, 4, "rigid"), (4, 1, "rigid"),
                                        (5, 2, "rigid"), (3, 0, "pressure_release"), (6, 3, "rigid"),
                                        (7, 2, "rigid"), (8, 0, "rigid"), (9, 4, "pressure_release")])
@@ -53,7 +69,8 @@ def test_gradient_matches_oracle_fp64(N, ckpt, bc):
     mf = _gpu_misfit(P, VX, EToV, m, src, rec, obs, N, "f64", ckpt, bc)
     J = float(mf.evaluate().item())
     g = mf.gradient().cpu().numpy()
-    assert abs(J - J0) < 1e-12 * abs(J0), (J, J0)
+    bar = _J_bar(VX, EToV, m, src, rec, obs, N, bc)
+    assert abs(J - J0) <= bar, (J, J0, bar)
     assert _rel(g, g0) < 1e-10, _rel(g, g0)
     # a second gradient of the same forward run: the last segment, which the
     # forward run recorded, is now recomputed (its records were overwritten
