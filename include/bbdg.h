@@ -132,6 +132,17 @@ int bbdg_nodal_create(bbdg_solver** out, int N, int dtype, int64_t K,
                       const int32_t* EToE, const int8_t* EToF, const int8_t* EToO,
                       const double* geo, const double* c, int bc, int device);
 
+/* Second dense nodal comparator, element per thread (Section 4.2 describes
+ * the paper's blocked "element-per-thread" nodal kernels): the same scheme,
+ * operators and field layout as bbdg_nodal_create, applied with vector FMAs by
+ * one thread per element, in blocks of output rows whose operator entries are
+ * shared by a wavefront of elements.  Same arguments and validation as
+ * bbdg_create; bbdg_rhs, bbdg_run, bbdg_work_bytes and bbdg_destroy accept
+ * it; bbdg_basis returns 2. */
+int bbdg_nodal_ept_create(bbdg_solver** out, int N, int dtype, int64_t K,
+                          const int32_t* EToE, const int8_t* EToF, const int8_t* EToO,
+                          const double* geo, const double* c, int bc, int device);
+
 /* The comparator's dense operators of order N, as built at create time (host,
  * caller-allocated): dr (3 x Np x Np) with Dr_i = V (D^i - D^0) V^{-1}, so that
  * grad f = sum_i grad(lambda_i) Dr_i f, and lift (Np x 4 Nfp), the face lifts
@@ -140,7 +151,8 @@ int bbdg_nodal_create(bbdg_solver** out, int N, int dtype, int64_t K,
  * face lattices. */
 int bbdg_nodal_operators(int N, double* dr, double* lift);
 
-/* 0 for a Bernstein-Bezier solver, 1 for a nodal comparator, BBDG_E_ARG for NULL. */
+/* 0 for a Bernstein-Bezier solver, 1 for the MFMA nodal comparator, 2 for the
+ * element-per-thread nodal comparator, BBDG_E_ARG for NULL. */
 int bbdg_basis(const bbdg_solver* s);
 
 /* Order, element type and element count of a solver. */

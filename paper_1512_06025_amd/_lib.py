@@ -35,6 +35,9 @@ SIGNATURES = {
     "bbdg_nodal_create": (_c.c_int, [_c.POINTER(_c.c_void_p), _c.c_int, _c.c_int, _c.c_int64,
                                      _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p,
                                      _c.c_int, _c.c_int]),
+    "bbdg_nodal_ept_create": (_c.c_int, [_c.POINTER(_c.c_void_p), _c.c_int, _c.c_int, _c.c_int64,
+                                         _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p,
+                                         _c.c_int, _c.c_int]),
     "bbdg_nodal_operators": (_c.c_int, [_c.c_int, _c.c_void_p, _c.c_void_p]),
     "bbdg_basis": (_c.c_int, [_c.c_void_p]),
     "bbdg_info": (_c.c_int, [_c.c_void_p, _c.POINTER(_c.c_int), _c.POINTER(_c.c_int),

@@ -8,7 +8,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbbdg.so")
-SOURCES = ["bb_stage.hip", "bb_adjoint.hip", "nodal_stage.hip", "copy_probe.hip", "bbdg_api.cpp"]
+SOURCES = ["bb_stage.hip", "bb_adjoint.hip", "nodal_stage.hip", "nodal_ept.hip", "copy_probe.hip",
+           "bbdg_api.cpp"]
 ARCH = "gfx950"
 
 FLAGS = [

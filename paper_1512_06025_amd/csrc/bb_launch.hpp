@@ -80,10 +80,6 @@ hipError_t launch_poison(const uint32_t* sync, T* a, int64_t n, hipStream_t stre
 hipError_t launch_wavelet(double* amp, int64_t nstages, double t0, int64_t step0, double dt, double f0, double ts,
                           hipStream_t stream);
 
-// Arguments of the dense nodal comparator stage kernel: the same fields,
-// geometry and connectivity plus the dense operators
-//   dr   [3][NpP][Kv]  Dr_i = V (D^i - D^0) V^{-1}, zero padded
-//   lift [NpP][Kl]     the four face lifts side by side, zero padded
 // One reverse stage of the discrete adjoint of the batched LSRK4 run.
 //   u = rb + b_s qb (qb completed with the neighbour terms of the previous
 //   reverse stage, z_in), qb <- qb + dt A^T u (own-element part), rb <- a_s u,
@@ -128,6 +124,11 @@ hipError_t launch_gradient_finalize(int64_t K, int64_t shots, const double* geo,
                                     const uint8_t* etofo, const double* gk, const double* gt, double* grad,
                                     hipStream_t stream);
 
+// Arguments of the dense nodal comparator stage kernels: the same fields,
+// geometry and connectivity plus the dense operators; for the MFMA kernel
+//   dr   [3][NpP][Kv]  Dr_i = V (D^i - D^0) V^{-1}, zero padded
+//   lift [NpP][Kl]     the four face lifts side by side, zero padded
+// (the element-per-thread kernel takes them in its own layout, below).
 template <typename T>
 struct NodalArgs {
   const T* qin;
@@ -148,6 +149,16 @@ struct NodalArgs {
 
 template <typename T>
 hipError_t launch_nodal_stage(int N, int mode, const NodalArgs<T>& a, hipStream_t stream);
+
+// Element-per-thread nodal comparator: rows per register block (the operator
+// layouts of its NodalArgs are built for it on the host, see nodal_ept.hip):
+// dr = opv [Np][NB B][4], lift = opl [4 Nfp][NB B], NB = ceil(Np / B).
+constexpr int ept_block_rows(int N, bool f64) {
+  return (N + 1) * (N + 2) * (N + 3) / 6 < (f64 ? 16 : 32) ? (N + 1) * (N + 2) * (N + 3) / 6 : (f64 ? 16 : 32);
+}
+
+template <typename T>
+hipError_t launch_nodal_ept(int N, int mode, const NodalArgs<T>& a, hipStream_t stream);
 
 hipError_t launch_copy_probe(const void* src, void* dst, size_t bytes, hipStream_t stream);
 

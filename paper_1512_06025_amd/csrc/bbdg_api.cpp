@@ -18,7 +18,7 @@ using namespace bbdg;
 
 struct bbdg_solver {
   int N = 0, dtype = 0, bc = 0, device = 0;
-  int basis = 0;  // 0 Bernstein-Bezier, 1 dense nodal comparator
+  int basis = 0;  // 0 Bernstein-Bezier, 1 dense nodal comparator (MFMA), 2 (element per thread)
   int64_t K = 0;
   void* d_dr = nullptr;    // nodal: [3][NpP][Kv] of the element type
   void* d_lift = nullptr;  // nodal: [NpP][Kl]
@@ -191,6 +191,7 @@ hipError_t launch_any(const bbdg_solver* s, int mode, const T* qin, T* qout, T* 
   a.rk_b = rk_b;
   a.dt = dt;
   a.read_res = read_res;
+  if (s->basis == 2) return launch_nodal_ept<T>(s->N, mode, a, st);
   return launch_nodal_stage<T>(s->N, mode, a, st);
 }
 
@@ -359,6 +360,24 @@ bool nodal_operators(int N, std::vector<double>& dr, std::vector<double>& lift) 
       for (int g = 0; g < Nfp; ++g) lift[(size_t)r * nd.Kl + f * Nfp + g] = Ln[(size_t)r * Nfp + g];
   }
   return true;
+}
+
+// The element-per-thread comparator's operator layouts (rows padded to whole
+// register blocks of B rows): opv [Np][NpB][4] = (Dr_1, Dr_2, Dr_3, 0)[i][j]
+// for input node j, opl [4 Nfp][NpB] = LIFT[i][m] for face node m.
+void ept_operators(int N, bool f64, const std::vector<double>& dr, const std::vector<double>& lift,
+                   std::vector<double>& opv, std::vector<double>& opl) {
+  const NodalDims nd = nodal_dims(N);
+  const int Np = np_of(N), Nfp = nfp_of(N);
+  const int B = ept_block_rows(N, f64);
+  const int NpB = (Np + B - 1) / B * B;
+  opv.assign((size_t)Np * NpB * 4, 0.0);
+  opl.assign((size_t)4 * Nfp * NpB, 0.0);
+  for (int j = 0; j < Np; ++j)
+    for (int i = 0; i < Np; ++i)
+      for (int d = 0; d < 3; ++d) opv[((size_t)j * NpB + i) * 4 + d] = dr[((size_t)d * nd.NpP + i) * nd.Kv + j];
+  for (int m = 0; m < 4 * Nfp; ++m)
+    for (int i = 0; i < Np; ++i) opl[(size_t)m * NpB + i] = lift[(size_t)i * nd.Kl + m];
 }
 
 template <typename T>
@@ -956,11 +975,17 @@ static int create_impl(bbdg_solver** out, int N, int dtype, int64_t K, const int
   ok = ok && hipMemcpy(s->d_etoe, EToE, (size_t)(4 * K) * sizeof(int32_t), hipMemcpyHostToDevice) == hipSuccess;
   ok = ok && hipMemcpy(s->d_etofo, fo.data(), fo.size(), hipMemcpyHostToDevice) == hipSuccess;
   ok = ok && hipMemcpy(s->d_tab, tab.data(), tab.size() * sizeof(uint16_t), hipMemcpyHostToDevice) == hipSuccess;
-  if (ok && basis == 1) {
+  if (ok && basis >= 1) {
     std::vector<double> dr, lift;
     if (!nodal_operators(N, dr, lift)) {
       free_solver(s);
       return BBDG_E_ARG;
+    }
+    if (basis == 2) {
+      std::vector<double> opv, opl;
+      ept_operators(N, dtype == BBDG_F64, dr, lift, opv, opl);
+      dr.swap(opv);
+      lift.swap(opl);
     }
     ok = dtype == BBDG_F64 ? (upload_as<double>(dr, &s->d_dr) && upload_as<double>(lift, &s->d_lift))
                            : (upload_as<float>(dr, &s->d_dr) && upload_as<float>(lift, &s->d_lift));
@@ -981,6 +1006,11 @@ int bbdg_create(bbdg_solver** out, int N, int dtype, int64_t K, const int32_t* E
 int bbdg_nodal_create(bbdg_solver** out, int N, int dtype, int64_t K, const int32_t* EToE, const int8_t* EToF,
                       const int8_t* EToO, const double* geo, const double* c, int bc, int device) {
   return create_impl(out, N, dtype, K, EToE, EToF, EToO, geo, c, bc, device, 1);
+}
+
+int bbdg_nodal_ept_create(bbdg_solver** out, int N, int dtype, int64_t K, const int32_t* EToE, const int8_t* EToF,
+                          const int8_t* EToO, const double* geo, const double* c, int bc, int device) {
+  return create_impl(out, N, dtype, K, EToE, EToF, EToO, geo, c, bc, device, 2);
 }
 
 int bbdg_nodal_operators(int N, double* dr, double* lift) {

@@ -87,7 +87,8 @@ class Solver:
     """One solver handle: order N, element type, mesh, wavespeed, boundary condition.
 
     basis="bb" is the Bernstein-Bezier solver; basis="nodal" the dense nodal
-    comparator (fields are then nodal values at the lattice points).
+    comparator applied by MFMA, basis="nodal_ept" the element-per-thread one
+    (fields are then nodal values at the lattice points).
     Field tensors are torch CUDA tensors of shape (4, K, Np) with dtype
     float64 (dtype="f64") or float32 (dtype="f32")."""
 
@@ -103,12 +104,13 @@ class Solver:
         self.device = torch.device("cuda", device)
         c = np.ascontiguousarray(np.broadcast_to(np.asarray(c, dtype=np.float64), (self.K,)))
         h = ctypes.c_void_p()
-        create = {"bb": load().bbdg_create, "nodal": load().bbdg_nodal_create}[basis]
+        create = {"bb": load().bbdg_create, "nodal": load().bbdg_nodal_create,
+                  "nodal_ept": load().bbdg_nodal_ept_create}[basis]
         self.basis = basis
         check(create(ctypes.byref(h), self.N, self.code, self.K,
                      mesh.EToE.ctypes.data, mesh.EToF.ctypes.data, mesh.EToO.ctypes.data,
                      mesh.geo.ctypes.data, c.ctypes.data, bcode, int(device)),
-              "bbdg_create" if basis == "bb" else "bbdg_nodal_create")
+              {"bb": "bbdg_create", "nodal": "bbdg_nodal_create", "nodal_ept": "bbdg_nodal_ept_create"}[basis])
         self._h = h
         self._work = None
 

@@ -167,9 +167,13 @@ def _lattice_vandermonde(N):
     return dg.bernstein_eval(N, np.array(bb.multi_indices(N), float) / N)
 
 
+NODAL_KINDS = ["nodal", "nodal_ept"]  # MFMA and element-per-thread comparators
+
+
+@pytest.mark.parametrize("basis", NODAL_KINDS)
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("N", list(range(1, 10)))
-def test_nodal_rhs_parity(N, dtype):
+def test_nodal_rhs_parity(N, dtype, basis):
     P, mesh, c, prob = _setup(2, N, drop_last=5)
     V = _lattice_vandermonde(N)
     cq = workload.random_coeffs(prob.K, prob.Np)
@@ -177,7 +181,7 @@ def test_nodal_rhs_parity(N, dtype):
     if dtype == "f32":
         x = x.astype(np.float32).astype(np.float64)
         cq = x @ np.linalg.inv(V).T
-    s = P.Solver(N, mesh, c, dtype=dtype, basis="nodal")
+    s = P.Solver(N, mesh, c, dtype=dtype, basis=basis)
     xd = _to_dev(x, dtype)
     for mode, kw in ((P.BBDG_RHS_VOLUME, dict(surface=False)),
                      (P.BBDG_RHS_SURFACE, dict(volume=False)),
@@ -185,12 +189,13 @@ def test_nodal_rhs_parity(N, dtype):
         got = _host(s.rhs(xd, mode))
         want = prob.rhs(cq, **kw) @ V.T
         err = _rel(got, want)
-        assert err < NODAL_TOL[dtype], (N, dtype, mode, err)
+        assert err < NODAL_TOL[dtype], (N, dtype, basis, mode, err)
     s.close()
 
 
+@pytest.mark.parametrize("basis", NODAL_KINDS)
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-def test_nodal_run_parity_c1(dtype):
+def test_nodal_run_parity_c1(dtype, basis):
     import paper_1512_06025_amd as P
     cfg, VX, EToV, c = workload.build_preset("c1")
     prob = dg.Problem(VX, EToV, cfg["N"], c)
@@ -201,9 +206,32 @@ def test_nodal_run_parity_c1(dtype):
         x0 = x0.astype(np.float32).astype(np.float64)
         q0 = x0 @ np.linalg.inv(V).T
     want = prob.lsrk4(q0, cfg["dt"], cfg["steps"]) @ V.T
-    s = P.Solver(cfg["N"], P.mesh_geometry(VX, EToV), c, dtype=dtype, basis="nodal")
+    s = P.Solver(cfg["N"], P.mesh_geometry(VX, EToV), c, dtype=dtype, basis=basis)
     xd = _to_dev(x0, dtype)
     s.run(xd, cfg["dt"], cfg["steps"])
     err = _rel(_host(xd), want)
-    assert err < NODAL_TOL[dtype], err
+    assert err < NODAL_TOL[dtype], (basis, err)
+    s.close()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("N", [3, 6, 9])
+def test_nodal_ept_stage_parity(N, dtype):
+    """One LSRK4 step of the element-per-thread comparator (fused volume,
+    flux, lift and update over several row blocks for N >= 3 in FP64) on a
+    ragged jittered mesh with c ~ U[1,3], against V (oracle step)."""
+    P, mesh, c, prob = _setup(3, N, drop_last=7)
+    V = _lattice_vandermonde(N)
+    cq = workload.random_coeffs(prob.K, prob.Np, seed=60 + N)
+    x = cq @ V.T
+    if dtype == "f32":
+        x = x.astype(np.float32).astype(np.float64)
+        cq = x @ np.linalg.inv(V).T
+    dt = 0.5 / (3 * 3.0 * (N + 1) ** 2)
+    want = prob.lsrk4(cq, dt, 1) @ V.T
+    s = P.Solver(N, mesh, c, dtype=dtype, basis="nodal_ept")
+    xd = _to_dev(x, dtype)
+    s.run(xd, dt, 1)
+    err = _rel(_host(xd), want)
+    assert err < NODAL_TOL[dtype], (N, dtype, err)
     s.close()
