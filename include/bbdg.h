@@ -47,7 +47,8 @@
  *   Ownership:   the caller owns every field, work and output buffer; the
  *                library owns only the device copies of geometry, connectivity
  *                and operator index tables, allocated in bbdg_create and freed
- *                in bbdg_destroy.
+ *                in bbdg_destroy, and, on every device it runs on, the static
+ *                work array of bbdg_run_noalloc (held until the process ends).
  *   Errors:      every int-returning call returns BBDG_OK (0) or a negative
  *                BBDG_E_* code; nothing throws across the ABI.  Arguments are
  *                validated before the device is touched.  A handle is not
@@ -76,6 +77,7 @@ extern "C" {
 #define BBDG_E_OUTSIDE (-10)  /* a point lies in no element of the mesh */
 #define BBDG_E_RESIDENT (-11) /* a persistent grid that cannot be co-resident on the device */
 #define BBDG_E_TIMEOUT (-12)  /* a grid-wide barrier of a persistent launch timed out (see bbdg_status) */
+#define BBDG_E_TOOBIG (-13)   /* the problem needs more work space than bbdg_run_noalloc holds */
 
 enum { BBDG_F64 = 0, BBDG_F32 = 1 };
 
@@ -137,8 +139,8 @@ int bbdg_nodal_create(bbdg_solver** out, int N, int dtype, int64_t K,
  * operators and field layout as bbdg_nodal_create, applied with vector FMAs by
  * one thread per element, in blocks of output rows whose operator entries are
  * shared by a wavefront of elements.  Same arguments and validation as
- * bbdg_create; bbdg_rhs, bbdg_run, bbdg_work_bytes and bbdg_destroy accept
- * it; bbdg_basis returns 2. */
+ * bbdg_create; bbdg_rhs, bbdg_run, bbdg_run_noalloc, bbdg_work_bytes and
+ * bbdg_destroy accept it; bbdg_basis returns 2. */
 int bbdg_nodal_ept_create(bbdg_solver** out, int N, int dtype, int64_t K,
                           const int32_t* EToE, const int8_t* EToF, const int8_t* EToO,
                           const double* geo, const double* c, int bc, int device);
@@ -172,6 +174,24 @@ size_t bbdg_work_bytes(const bbdg_solver* s);
  * contents on entry are ignored.  steps >= 0, dt finite. */
 int bbdg_run(bbdg_solver* s, void* q, void* work, double t0, double dt, int64_t steps,
              void* stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): bbdg_run with the
+ * work space taken from a static device array of BBDG_NOALLOC_WORK_BYTES
+ * (64 MiB) that the library holds on every device it runs on until the
+ * process ends, so that the call itself allocates nothing (no hipMalloc,
+ * hipFree or allocating library routine).  Same arguments, kernels and
+ * results as bbdg_run without `work`: q is the caller's device (4, K, Np)
+ * field, in/out.  Fails with BBDG_E_TOOBIG, before touching the device, when
+ * bbdg_work_bytes(s) exceeds BBDG_NOALLOC_WORK_BYTES (e.g. FP64 with
+ * 4 K Np > 1,048,576), and with BBDG_E_DEVICE if the array's address could
+ * not be looked up when the first solver on the device was created.  The
+ * array's contents on entry are ignored (nothing in it needs to start at
+ * zero).  Every call on one device shares that device's array: calls that
+ * overlap in time on one device (several streams or threads, any handles)
+ * race and give undefined results; serialise them. */
+#define BBDG_NOALLOC_WORK_BYTES ((size_t)64 << 20)
+int bbdg_run_noalloc(bbdg_solver* s, void* q, double t0, double dt, int64_t steps, void* stream);
 
 /* Output stores of the FP64 stage kernel that bbdg_run launches (a
  * performance choice; the arithmetic and results are identical):

@@ -19,8 +19,9 @@ ERRORS = {
     0: "BBDG_OK", -1: "BBDG_E_ARG", -2: "BBDG_E_ORDER", -3: "BBDG_E_MESH",
     -4: "BBDG_E_NONFINITE", -5: "BBDG_E_DTYPE", -6: "BBDG_E_BC", -7: "BBDG_E_DEVICE",
     -8: "BBDG_E_LAUNCH", -9: "BBDG_E_MODE", -10: "BBDG_E_OUTSIDE", -11: "BBDG_E_RESIDENT",
-    -12: "BBDG_E_TIMEOUT",
+    -12: "BBDG_E_TIMEOUT", -13: "BBDG_E_TOOBIG",
 }
+BBDG_NOALLOC_WORK_BYTES = 64 << 20
 
 # name -> (restype, argtypes)
 _c = ctypes
@@ -46,6 +47,8 @@ SIGNATURES = {
     "bbdg_work_bytes": (_c.c_size_t, [_c.c_void_p]),
     "bbdg_run": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_double, _c.c_double,
                             _c.c_int64, _c.c_void_p]),
+    "bbdg_run_noalloc": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_double, _c.c_double, _c.c_int64,
+                                    _c.c_void_p]),
     "bbdg_set_store_policy": (_c.c_int, [_c.c_void_p, _c.c_int]),
     "bbdg_nontemporal_stores": (_c.c_int, [_c.c_void_p]),
     "bbdg_locate_points": (_c.c_int, [_c.c_int64, _c.c_int64, _c.c_void_p, _c.c_void_p, _c.c_int64,

@@ -7,6 +7,7 @@
 #include <array>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -15,6 +16,15 @@
 #include "bb_launch.hpp"
 
 using namespace bbdg;
+
+// Work space of bbdg_run_noalloc, for callers that cannot allocate device
+// memory: a file-scope device array of BBDG_NOALLOC_WORK_BYTES, one copy per
+// device, held from the loading of this code object until the process ends.
+// On the host its name is only a stand-in symbol, never a device address:
+// the address of each device's copy is looked up once (bind_scratch, with
+// that device current, when the first solver on it is created) and only
+// that address is handed to kernels and copies.
+static __device__ __align__(256) unsigned char scratch[BBDG_NOALLOC_WORK_BYTES];
 
 struct bbdg_solver {
   int N = 0, dtype = 0, bc = 0, device = 0;
@@ -138,6 +148,38 @@ thread_local int g_last_hip_error = 0;
 int hip_fail(hipError_t e, int code) {
   g_last_hip_error = (int)e;
   return code;
+}
+
+// Device address of each device's copy of `scratch` (null until bound), and
+// the HIP error of a failed lookup.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+hipError_t g_scratch_err[kMaxDevices] = {};
+
+// Looks up the current device's copy of `scratch`; called with `device`
+// current.  A failed lookup only disables bbdg_run_noalloc on that device.
+void bind_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device]) return;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e == hipSuccess && p) {
+    g_scratch_ptr[device] = p;
+  } else {
+    g_scratch_err[device] = e == hipSuccess ? hipErrorInvalidSymbol : e;
+    (void)hipGetLastError();
+  }
+}
+
+// The bound address of `device`'s copy, or null (then *err says why).
+void* scratch_of(int device, hipError_t* err) {
+  *err = hipErrorInvalidDevice;
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  *err = g_scratch_err[device];
+  return g_scratch_ptr[device];
 }
 
 // Non-temporal output stores for the FP64 stage when the three field sets a
@@ -775,6 +817,7 @@ const char* bbdg_strerror(int code) {
     case BBDG_E_OUTSIDE: return "point outside the mesh";
     case BBDG_E_RESIDENT: return "persistent grid cannot be co-resident";
     case BBDG_E_TIMEOUT: return "grid barrier timed out (persistent grid not co-resident); results are NaN";
+    case BBDG_E_TOOBIG: return "work space larger than the static array of bbdg_run_noalloc";
     default: return "unknown error code";
   }
 }
@@ -947,6 +990,7 @@ static int create_impl(bbdg_solver** out, int N, int dtype, int64_t K, const int
   }
 
   if (hipSetDevice(device) != hipSuccess) return BBDG_E_DEVICE;
+  bind_scratch(device);
   bbdg_solver* s = new (std::nothrow) bbdg_solver();
   if (!s) return BBDG_E_DEVICE;
   s->N = N;
@@ -1084,6 +1128,19 @@ int bbdg_run(bbdg_solver* s, void* q, void* work, double t0, double dt, int64_t 
   return run_typed<float>(s, (float*)q, (float*)work, dt, steps, st);
 }
 
+int bbdg_run_noalloc(bbdg_solver* s, void* q, double t0, double dt, int64_t steps, void* stream) {
+  if (!s || !q || steps < 0) return BBDG_E_ARG;
+  if (!std::isfinite(t0) || !std::isfinite(dt)) return BBDG_E_NONFINITE;
+  if (bbdg_work_bytes(s) > BBDG_NOALLOC_WORK_BYTES) return BBDG_E_TOOBIG;
+  hipError_t err = hipSuccess;
+  void* work = scratch_of(s->device, &err);
+  if (!work) return hip_fail(err, BBDG_E_DEVICE);
+  if (hipSetDevice(s->device) != hipSuccess) return BBDG_E_DEVICE;
+  hipStream_t st = (hipStream_t)stream;
+  if (s->dtype == BBDG_F64) return run_typed<double>(s, (double*)q, (double*)work, dt, steps, st);
+  return run_typed<float>(s, (float*)q, (float*)work, dt, steps, st);
+}
+
 int bbdg_locate_points(int64_t K, int64_t Nv, const double* VX, const int32_t* EToV, int64_t n, const double* xyz,
                        int32_t* elem, double* bary) {
   if (K <= 0 || Nv <= 0 || n < 0 || !VX || !EToV || (n > 0 && (!xyz || !elem || !bary))) return BBDG_E_ARG;
@@ -1196,13 +1253,13 @@ int bbdg_run_batched(bbdg_solver* s, void* q, int64_t shots, const int32_t* src_
                                   (const float*)rec_coef, (float*)traces, (float*)work, t0, dt, steps, wpb, st);
 }
 
-int bbdg_tune_batched(bbdg_solver* s, int64_t shots, void* scratch, int* wpb, void* stream) {
-  if (!s || !scratch || !wpb || s->basis != 0 || !batched_shape_ok(s, shots)) return BBDG_E_ARG;
-  if (((uintptr_t)scratch) % 256 != 0) return BBDG_E_ARG;
+int bbdg_tune_batched(bbdg_solver* s, int64_t shots, void* tune_space, int* wpb, void* stream) {
+  if (!s || !tune_space || !wpb || s->basis != 0 || !batched_shape_ok(s, shots)) return BBDG_E_ARG;
+  if (((uintptr_t)tune_space) % 256 != 0) return BBDG_E_ARG;
   if (hipSetDevice(s->device) != hipSuccess) return BBDG_E_DEVICE;
   hipStream_t st = (hipStream_t)stream;
   const size_t state = (size_t)shots * 4 * (size_t)s->K * np_of(s->N) * elem_size(s->dtype);
-  char* q = (char*)scratch;
+  char* q = (char*)tune_space;
   char* work = q + ((state + 255) / 256) * 256;
   if (hipMemsetAsync(q, 0, state, st) != hipSuccess) return BBDG_E_DEVICE;
   hipEvent_t e0, e1;

@@ -159,6 +159,8 @@ def test_null_handles_and_strerror(lib):
     assert lib.bbdg_status(None) == -1
     assert lib.bbdg_set_barrier_timeout(None, 1.0) == -1
     assert lib.bbdg_strerror(-12) != b"unknown error code"
+    assert lib.bbdg_run_noalloc(None, None, 0.0, 1.0, 1, None) == -1
+    assert lib.bbdg_strerror(-13) != b"unknown error code"
 
 
 # -- host utilities of the batched path (no device involved) ---------------------
