@@ -8,7 +8,9 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libbbdg.so")
+# BBDG_LIBRARY may name another build of the same library (the host-sanitized
+# one of sanitize_build.py); by default the in-tree libbbdg.so is loaded.
+LIB_PATH = os.environ.get("BBDG_LIBRARY") or os.path.join(HERE, "libbbdg.so")
 
 BBDG_F64, BBDG_F32 = 0, 1
 BBDG_BC_RIGID, BBDG_BC_PRESSURE_RELEASE = 0, 1

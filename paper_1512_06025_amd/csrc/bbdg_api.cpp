@@ -989,8 +989,6 @@ static int create_impl(bbdg_solver** out, int N, int dtype, int64_t K, const int
     }
   }
 
-  if (hipSetDevice(device) != hipSuccess) return BBDG_E_DEVICE;
-  bind_scratch(device);
   bbdg_solver* s = new (std::nothrow) bbdg_solver();
   if (!s) return BBDG_E_DEVICE;
   s->N = N;
@@ -999,6 +997,7 @@ static int create_impl(bbdg_solver** out, int N, int dtype, int64_t K, const int
   s->device = device;
   s->K = K;
   s->basis = basis;
+  // everything the host builds comes before the first device call
   s->h_geo.assign(geo, geo + 10 * K);
   s->h_etoe.assign(EToE, EToE + 4 * K);
   s->h_J.resize((size_t)K);
@@ -1009,6 +1008,24 @@ static int create_impl(bbdg_solver** out, int N, int dtype, int64_t K, const int
   for (int64_t slot = 0; slot < 4 * K; ++slot)
     fo[(size_t)slot] = EToE[slot] >= 0 ? (uint8_t)((EToF[slot] & 3) | (EToO[slot] << 2)) : 0;
   const std::vector<uint16_t> tab = build_tables(N);
+  std::vector<double> dr, lift;  // dense operators of the nodal comparators
+  if (basis >= 1) {
+    if (!nodal_operators(N, dr, lift)) {
+      delete s;
+      return BBDG_E_ARG;
+    }
+    if (basis == 2) {
+      std::vector<double> opv, opl;
+      ept_operators(N, dtype == BBDG_F64, dr, lift, opv, opl);
+      dr.swap(opv);
+      lift.swap(opl);
+    }
+  }
+  if (hipSetDevice(device) != hipSuccess) {
+    delete s;
+    return BBDG_E_DEVICE;
+  }
+  bind_scratch(device);
   bool ok = hipMalloc(&s->d_geo, dgeo.size() * sizeof(double)) == hipSuccess &&
             hipMalloc(&s->d_etoe, (size_t)(4 * K) * sizeof(int32_t)) == hipSuccess &&
             hipMalloc(&s->d_etofo, fo.size()) == hipSuccess &&
@@ -1020,17 +1037,6 @@ static int create_impl(bbdg_solver** out, int N, int dtype, int64_t K, const int
   ok = ok && hipMemcpy(s->d_etofo, fo.data(), fo.size(), hipMemcpyHostToDevice) == hipSuccess;
   ok = ok && hipMemcpy(s->d_tab, tab.data(), tab.size() * sizeof(uint16_t), hipMemcpyHostToDevice) == hipSuccess;
   if (ok && basis >= 1) {
-    std::vector<double> dr, lift;
-    if (!nodal_operators(N, dr, lift)) {
-      free_solver(s);
-      return BBDG_E_ARG;
-    }
-    if (basis == 2) {
-      std::vector<double> opv, opl;
-      ept_operators(N, dtype == BBDG_F64, dr, lift, opv, opl);
-      dr.swap(opv);
-      lift.swap(opl);
-    }
     ok = dtype == BBDG_F64 ? (upload_as<double>(dr, &s->d_dr) && upload_as<double>(lift, &s->d_lift))
                            : (upload_as<float>(dr, &s->d_dr) && upload_as<float>(lift, &s->d_lift));
   }

@@ -121,6 +121,28 @@ def test_create_validation_errors(lib):
     assert lib.bbdg_create(ctypes.byref(h), 3, 0, m.K, None, None, None, None, None, 0, 0) == -1
 
 
+@pytest.mark.parametrize("N", list(range(1, 10)))
+def test_create_builds_host_tables_before_the_device(lib, N):
+    """Valid arguments to the three create calls: every host-side table (flux
+    weights, index tables, the dense nodal operators in both comparator
+    layouts) is built before the first device call, so without a GPU the
+    calls build them and then fail with BBDG_E_DEVICE; with a GPU they
+    succeed and the handle is destroyed."""
+    VX, EToV = workload.kuhn_cube_mesh(2, 0.1, drop_last=3)
+    m = P.mesh_geometry(VX, EToV)
+    c = np.linspace(1.0, 2.0, m.K)
+    for create in (lib.bbdg_create, lib.bbdg_nodal_create, lib.bbdg_nodal_ept_create):
+        for dtype in (_lib.BBDG_F64, _lib.BBDG_F32):
+            h = ctypes.c_void_p()
+            rc = create(ctypes.byref(h), N, dtype, m.K, m.EToE.ctypes.data, m.EToF.ctypes.data,
+                        m.EToO.ctypes.data, m.geo.ctypes.data, c.ctypes.data, _lib.BBDG_BC_RIGID, 0)
+            assert rc in (0, -7), rc
+            if rc == 0:
+                assert lib.bbdg_destroy(h) == 0
+            else:
+                assert not h.value
+
+
 def test_mesh_geometry_errors(lib):
     VX, EToV = workload.kuhn_cube_mesh(1)
     K, Nv = EToV.shape[0], VX.shape[0]
