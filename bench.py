@@ -14,8 +14,8 @@ bracketed by torch.cuda.synchronize() and HIP events recorded on the stream
 the kernels run on; the reported time is the median run.
 
 Prints one JSON line: DoF-stage updates/s (4 K Np per stage) for FP64 (the
-headline value), the FP32 run on the same workload, the dense nodal
-comparator, the order sweep on 32^3 x 6 = 196,608 tets (the configuration
+headline value), the FP32 run on the same workload, the two dense nodal
+comparators (MFMA, and element per thread), the order sweep on 32^3 x 6 = 196,608 tets (the configuration
 whose fields do not fit in the 256 MB last-level cache, where the stage
 kernel's roofline placement is taken), the 64-shot batched workload, the
 misfit gradient, a streaming-copy probe, and the FP64 CPU oracle timed on
@@ -140,6 +140,26 @@ def roofline_obj(N, dtype, K, stage_us, nt, workload_tag, cache_assisted):
             "cache_assisted": cache_assisted}
 
 
+def nodal_entry(kind, N, dtype, K, stage_us, finite):
+    """Throughput of a dense nodal comparator stage: the MFMA kernel ("nodal",
+    24 Np^2 + 32 Np Nfp FLOP per element: three derivative matrices on four
+    fields and the four-face lift, against the dense MFMA peak of its type) or
+    the element-per-thread kernel ("nodal_ept", which applies the derivative
+    matrices to p and to the three h_d = grad(lambda_d).u only, 12 Np^2 + 32
+    Np Nfp FLOP, against the vector FMA peak of its type)."""
+    Np = (N + 1) * (N + 2) * (N + 3) // 6
+    Nfp = (N + 1) * (N + 2) // 2
+    if kind == "nodal":
+        flop = K * (24 * Np * Np + 32 * Np * Nfp)
+        peak_key, peak = "mfma_peak_tflops", (78.6 if dtype == "f64" else 157.3)
+    else:
+        flop = K * (12 * Np * Np + 32 * Np * Nfp)
+        peak_key, peak = "vector_peak_tflops", (78.6 if dtype == "f64" else 157.3)
+    tf = flop / (stage_us * 1e-6) / 1e12
+    return {"stage_us": stage_us, "tflops": tf, peak_key: peak, "peak_frac": tf / peak, "finite": finite,
+            "dof_stage_per_s": 4.0 * K * Np / (stage_us * 1e-6)}
+
+
 def time_c3(P, torch, workload, ic, orders, dtypes, steps, nodal_steps, warmup):
     """Order sweep on 32^3 x 6 = 196,608 tets, c ~ U[1,3], Gaussian pulse:
     per-stage time and HBM roofline placement of the BB stage for each
@@ -165,17 +185,14 @@ def time_c3(P, torch, workload, ic, orders, dtypes, steps, nodal_steps, warmup):
             row[dtype] = r
         if nodal_steps > 0:
             x0 = ic.initial_state(N, VX, EToV, workload.INITIAL_FIELDS[cfg["ic"]], basis="nodal")
-            Nfp = (N + 1) * (N + 2) // 2
-            flop = K * (24 * Np * Np + 32 * Np * Nfp)
             for dtype in dtypes:
-                med, runs, ok, _, _ = time_solver(P, torch, N, mesh, c, x0, dt, nodal_steps, 0, dtype,
-                                                  basis="nodal")
-                st = med * 1e3 / (5 * nodal_steps)
-                peak = 78.6 if dtype == "f64" else 157.3
-                tf = flop / (st * 1e-6) / 1e12
-                row["nodal_" + dtype] = {"stage_us": st, "tflops": tf, "mfma_peak_tflops": peak,
-                                         "mfma_frac": tf / peak, "finite": ok,
-                                         "bb_speedup": st / row[dtype]["avg_launch_us"]}
+                for kind in ("nodal", "nodal_ept"):
+                    med, runs, ok, _, _ = time_solver(P, torch, N, mesh, c, x0, dt, nodal_steps, 0, dtype,
+                                                      basis=kind)
+                    st = med * 1e3 / (5 * nodal_steps)
+                    e = nodal_entry(kind, N, dtype, K, st, ok)
+                    e["bb_speedup"] = st / row[dtype]["avg_launch_us"]
+                    row[kind + "_" + dtype] = e
         out["orders"][str(N)] = row
         gc.collect()
     return out
@@ -481,18 +498,16 @@ def main():
     if "nodal" in legs:
         x0 = ic.initial_state(N, VX, EToV, workload.INITIAL_FIELDS[cfg["ic"]], basis="nodal")
         nod = {}
-        for dtn in ("f64", "f32"):
-            msn, runsn, okn, _, _ = time_solver(P, torch, N, mesh, c, x0, dt, args.steps, args.warmup, dtn,
-                                                basis="nodal")
-            flop = K * (24 * Np * Np + 32 * Np * Nfp)  # dense volume + lift per stage
-            peak = 78.6 if dtn == "f64" else 157.3
-            tf = flop * stages / (msn * 1e-3) / 1e12
-            e = {"value": dof * stages / (msn * 1e-3), "stage_us": msn * 1e3 / stages, "tflops": tf,
-                 "mfma_frac": tf / peak, "finite": okn}
-            bb = ms64 if dtn == "f64" else out.get("fp32", {}).get("ms_per_step", 0) * args.steps
-            if bb:
-                e["bb_speedup"] = msn / bb
-            nod[dtn] = e
+        for kind in ("nodal", "nodal_ept"):
+            for dtn in ("f64", "f32"):
+                msn, runsn, okn, _, _ = time_solver(P, torch, N, mesh, c, x0, dt, args.steps, args.warmup, dtn,
+                                                    basis=kind)
+                e = nodal_entry(kind, N, dtn, K, msn * 1e3 / stages, okn)
+                e["value"] = dof * stages / (msn * 1e-3)
+                bb = ms64 if dtn == "f64" else out.get("fp32", {}).get("ms_per_step", 0) * args.steps
+                if bb:
+                    e["bb_speedup"] = msn / bb
+                nod[dtn if kind == "nodal" else "ept_" + dtn] = e
         out["nodal"] = nod
     del q64
     if "c3" in legs:

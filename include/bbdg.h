@@ -138,7 +138,9 @@ int bbdg_nodal_create(bbdg_solver** out, int N, int dtype, int64_t K,
  * the paper's blocked "element-per-thread" nodal kernels): the same scheme,
  * operators and field layout as bbdg_nodal_create, applied with vector FMAs by
  * one thread per element, in blocks of output rows whose operator entries are
- * shared by a wavefront of elements.  Same arguments and validation as
+ * shared by a wavefront of elements, after a flux kernel that writes the
+ * upwind flux of every face node to a buffer the handle owns (4 x K x 4 Nfp
+ * elements of the element type, allocated here).  Same arguments and validation as
  * bbdg_create; bbdg_rhs, bbdg_run, bbdg_run_noalloc, bbdg_work_bytes and
  * bbdg_destroy accept it; bbdg_basis returns 2. */
 int bbdg_nodal_ept_create(bbdg_solver** out, int N, int dtype, int64_t K,

@@ -140,6 +140,7 @@ struct NodalArgs {
   const uint16_t* tab;
   const T* dr;
   const T* lift;
+  T* flux;  // element-per-thread comparator: its face-node flux buffer (4, K, 4 Nfp)
   int64_t K;
   T rk_a, rk_b, dt;
   int read_res;
@@ -152,7 +153,8 @@ hipError_t launch_nodal_stage(int N, int mode, const NodalArgs<T>& a, hipStream_
 
 // Element-per-thread nodal comparator: rows per register block (the operator
 // layouts of its NodalArgs are built for it on the host, see nodal_ept.hip):
-// dr = opv [Np][NB B][4], lift = opl [4 Nfp][NB B], NB = ceil(Np / B).
+// dr = opv [Np][NB B][4], lift = opl [4 Nfp][NB B], NB = ceil(Np / B); it
+// launches a flux kernel (writing flux) and the element-per-thread kernel.
 constexpr int ept_block_rows(int N, bool f64) {
   return (N + 1) * (N + 2) * (N + 3) / 6 < (f64 ? 16 : 32) ? (N + 1) * (N + 2) * (N + 3) / 6 : (f64 ? 16 : 32);
 }

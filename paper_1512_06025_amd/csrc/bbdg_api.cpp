@@ -32,6 +32,7 @@ struct bbdg_solver {
   int64_t K = 0;
   void* d_dr = nullptr;    // nodal: [3][NpP][Kv] of the element type
   void* d_lift = nullptr;  // nodal: [NpP][Kl]
+  void* d_flux = nullptr;  // element-per-thread nodal: face-node fluxes (4, K, 4 Nfp)
   double* d_geo = nullptr;     // K x kGeoStride (see bb_common.hpp)
   int32_t* d_etoe = nullptr;   // K x 4
   uint8_t* d_etofo = nullptr;  // K x 4
@@ -438,6 +439,7 @@ NodalArgs<T> nodal_args(const bbdg_solver* s) {
   a.tab = s->d_tab;
   a.dr = (const T*)s->d_dr;
   a.lift = (const T*)s->d_lift;
+  a.flux = (T*)s->d_flux;
   a.K = s->K;
   a.bc = s->bc;
   return a;
@@ -451,6 +453,7 @@ void free_solver(bbdg_solver* s) {
   if (s->d_tab) (void)hipFree(s->d_tab);
   if (s->d_dr) (void)hipFree(s->d_dr);
   if (s->d_lift) (void)hipFree(s->d_lift);
+  if (s->d_flux) (void)hipFree(s->d_flux);
   if (s->d_sync) (void)hipFree(s->d_sync);
   delete s;
 }
@@ -1040,6 +1043,8 @@ static int create_impl(bbdg_solver** out, int N, int dtype, int64_t K, const int
     ok = dtype == BBDG_F64 ? (upload_as<double>(dr, &s->d_dr) && upload_as<double>(lift, &s->d_lift))
                            : (upload_as<float>(dr, &s->d_dr) && upload_as<float>(lift, &s->d_lift));
   }
+  if (ok && basis == 2)
+    ok = hipMalloc(&s->d_flux, (size_t)(4 * 4 * K) * nfp_of(N) * elem_size(dtype)) == hipSuccess;
   if (!ok) {
     free_solver(s);
     return BBDG_E_DEVICE;

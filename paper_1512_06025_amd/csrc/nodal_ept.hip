@@ -2,26 +2,39 @@
 //
 // The paper's second nodal baseline (Section 4.2, "element-per-thread"): every
 // thread owns one element and applies the dense derivative and lift matrices
-// to it in row blocks, the operator entries of a block being shared by all
-// threads, so that each entry fetched is reused by a whole wavefront of
-// elements.  Here the entries are wave-uniform scalar loads (SGPR operands of
-// v_fma, through the scalar cache) instead of blocks staged in shared memory,
-// and the 64 lanes of a wave are 64 elements.  The scheme is the same as the
-// Bernstein-Bezier path and the MFMA comparator (Section 2 upwind flux, strong
-// form of Section 3) in the Lagrange basis of the equispaced lattice:
+// to it in blocks of output rows, the operator entries of a block being
+// shared by all threads, so that each entry fetched is reused by a whole
+// wavefront of elements.  Here the entries are wave-uniform scalar loads
+// (SGPR operands of v_fma, through the scalar cache) instead of blocks staged
+// in shared memory, and the 64 lanes of a wave are 64 consecutive elements.
+// As in the paper the surface work is split: a flux kernel writes the upwind
+// flux of every face node to a buffer, and the element-per-thread kernel
+// applies the derivative matrices, the lift and the LSRK4 update.  The scheme
+// is the one of the Bernstein-Bezier path and of the MFMA comparator (Section
+// 2 upwind flux, strong form of Section 3) in the Lagrange basis of the
+// equispaced lattice:
 //   grad p = sum_{d=1..3} grad(lambda_d) (Dr_d p),
 //   div u  = sum_{d=1..3} Dr_d h_d,  h_d = grad(lambda_d) . u  (per node),
 //   rhs    = (-kappa div u, -grad p) + LIFT (sp, g_f su) on the 4 Nfp face nodes,
-// with Dr_d = V (D^d - D^0) V^{-1} and LIFT = [V E_L^f L_0 Vf^{-1}]_f.  Per row
-// block of B output nodes a thread keeps 4 B accumulators in registers; the
-// input values (own nodes, own and neighbour face traces and the upwind flux)
-// are re-read and recomputed for every block (the price of the blocking that
-// the paper notes), through L1/L2.  Volume, flux, lift and the LSRK4 update
-// run in one kernel (the paper used separate flux and lift kernels).
+// with Dr_d = V (D^d - D^0) V^{-1} and LIFT = [V E_L^f L_0 Vf^{-1}]_f.
+//
+// Data movement of the element-per-thread kernel: the inputs of an element
+// (its 4 Np coefficients, then its 4 x 4 Nfp flux values) are read in chunks
+// of J nodes for the wave's 64 elements with coalesced loads (each element's
+// J values are contiguous) into a per-wave LDS buffer laid out node-major,
+// [field][node][element], from which every lane reads its own element with
+// conflict-free accesses.  Each block of B output rows keeps 4 B accumulators
+// in registers and re-reads the chunks (the redundant loads of the blocking
+// the paper notes, here from L2).  The block's right-hand side goes back
+// through the same LDS buffer so that the LSRK4 update reads and writes the
+// fields with coalesced accesses.
 //
 // Operator layouts (built on the host, rows padded with zeros to NB B):
 //   opv [Np][NB B][4]:  (Dr_1, Dr_2, Dr_3, 0) of row i for input node j
 //   opl [4 Nfp][NB B]:  LIFT row i for face node m = f Nfp + g
+// Flux buffer (library-owned): F (4, K, 4 Nfp) of the element type, the
+// components (sp, g_x su, g_y su, g_z su) of face node m of element k at
+// F[c][k 4 Nfp + m].
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -30,53 +43,144 @@
 
 namespace bbdg {
 
-template <int N, typename T, int MODE>
-__global__ __launch_bounds__(256) void nodal_ept_kernel(NodalArgs<T> A, const T* __restrict__ opv,
-                                                        const T* __restrict__ opl, int64_t blocks) {
-  constexpr int Np = np_of(N), Nfp = nfp_of(N);
-  constexpr int B = ept_block_rows(N, sizeof(T) == 8);
-  constexpr int NB = (Np + B - 1) / B, NpB = NB * B;
-  constexpr bool kVol = (MODE != kRhsSurface);
-  constexpr bool kSurf = (MODE != kRhsVolume);
-  constexpr TabLayout L = tab_layout(N);
+namespace {
 
+__device__ __forceinline__ void ept_wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+}  // namespace
+
+// Upwind flux on every face node (one thread per element face node): own
+// trace, the neighbour's through the orientation tables or the boundary
+// mirror, then sp = a_p [[p]] - kappa/2 g.[[u]] and su = b_u g.[[u]] - [[p]]/2
+// (the weights of kGeoStride), stored as (sp, g su).
+template <int N, typename T>
+__global__ __launch_bounds__(256) void ept_flux_kernel(NodalArgs<T> A, T* __restrict__ F) {
+  constexpr int Np = np_of(N), Nfp = nfp_of(N), NL = 4 * Nfp;
+  constexpr TabLayout L = tab_layout(N);
   __shared__ uint16_t t_nbr[24 * Nfp];
   __shared__ uint16_t t_fnode[4 * Nfp];
   for (int i = threadIdx.x; i < 24 * Nfp; i += 256) t_nbr[i] = A.tab[L.nbrnode + i];
   for (int i = threadIdx.x; i < 4 * Nfp; i += 256) t_fnode[i] = A.tab[L.fnode + i];
   __syncthreads();
+  const int64_t K = A.K;
+  const int64_t items = K * NL;
+  const uint32_t KNp = (uint32_t)(K * Np);
+  const size_t KL = (size_t)K * NL;
+  for (int64_t it = (int64_t)blockIdx.x * 256 + threadIdx.x; it < items; it += (int64_t)gridDim.x * 256) {
+    const int64_t e = it / NL;
+    const int m = (int)(it - e * NL);
+    const int f = m / Nfp, g = m - f * Nfp;
+    const double* ge = A.geo + e * kGeoStride;
+    double lx, ly, lz;  // grad lambda_f
+    if (f == 0) {
+      lx = -(ge[0] + ge[3] + ge[6]);
+      ly = -(ge[1] + ge[4] + ge[7]);
+      lz = -(ge[2] + ge[5] + ge[8]);
+    } else {
+      lx = ge[3 * (f - 1)];
+      ly = ge[3 * (f - 1) + 1];
+      lz = ge[3 * (f - 1) + 2];
+    }
+    const T gx = (T)(-2.0 * lx), gy = (T)(-2.0 * ly), gz = (T)(-2.0 * lz);
+    const uint32_t own = (uint32_t)e * Np + t_fnode[m];
+    const T pm = A.qin[own], um = A.qin[KNp + own], vm = A.qin[2 * KNp + own], wm = A.qin[3 * KNp + own];
+    const T gum = gx * um + gy * vm + gz * wm;
+    const int32_t nb = A.etoe[e * 4 + f];
+    T jp, jgu;
+    if (nb >= 0) {
+      const uint32_t info = A.etofo[e * 4 + f];
+      const uint32_t o = (uint32_t)nb * Np + t_nbr[((info & 3) * 6 + (info >> 2)) * Nfp + g];
+      jp = A.qin[o] - pm;
+      jgu = gx * A.qin[KNp + o] + gy * A.qin[2 * KNp + o] + gz * A.qin[3 * KNp + o] - gum;
+    } else if (A.bc == 0) {  // rigid wall mirror
+      jp = 0;
+      jgu = (T)(-2) * gum;
+    } else {  // pressure-release mirror
+      jp = (T)(-2) * pm;
+      jgu = 0;
+    }
+    const T sp = (T)ge[10 + f] * jp - (T)(0.5 * ge[9]) * jgu;
+    const T su = (T)ge[14 + f] * jgu - (T)0.5 * jp;
+    F[it] = sp;
+    F[KL + it] = gx * su;
+    F[2 * KL + it] = gy * su;
+    F[3 * KL + it] = gz * su;
+  }
+}
+
+// Chunk of J nodes per staging round and LDS row padding: rows of 64 + PAD
+// values, so that the staging writes (J consecutive nodes of one element per
+// J lanes) spread over the banks.
+template <typename T>
+struct EptStage {
+  static constexpr int J = sizeof(T) == 8 ? 8 : 16;
+  static constexpr int PAD = sizeof(T) == 8 ? 8 : 4;
+  static constexpr int ROW = 64 + PAD;
+};
+
+// Stages values [n0, n0 + J) of the 4 arrays src + c * cstride (element k's
+// values at k * len) for the wave's elements e0 .. e0 + 63 into
+// s[c][jj][lane]; out-of-range entries read as zero.
+template <typename T>
+__device__ __forceinline__ void ept_stage(T* s, const T* src, size_t cstride, int len, int n0, int64_t e0, int64_t K,
+                                          int lane) {
+  constexpr int J = EptStage<T>::J, ROW = EptStage<T>::ROW;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+#pragma unroll
+    for (int it = 0; it < J; ++it) {
+      const int idx = it * 64 + lane;
+      const int el = idx / J, jj = idx % J;
+      const int n = n0 + jj;
+      T v = 0;
+      if (n < len && e0 + el < K) v = src[c * cstride + (size_t)(e0 + el) * len + n];
+      s[(c * J + jj) * ROW + el] = v;
+    }
+  }
+}
+
+template <int N, typename T, int MODE>
+__global__ __launch_bounds__(256) void nodal_ept_kernel(NodalArgs<T> A, const T* __restrict__ opv,
+                                                        const T* __restrict__ opl, const T* __restrict__ F,
+                                                        int64_t blocks) {
+  constexpr int Np = np_of(N), Nfp = nfp_of(N), NL = 4 * Nfp;
+  constexpr int B = ept_block_rows(N, sizeof(T) == 8);
+  constexpr int NB = (Np + B - 1) / B, NpB = NB * B;
+  constexpr int J = EptStage<T>::J, ROW = EptStage<T>::ROW;
+  constexpr bool kVol = (MODE != kRhsSurface);
+  constexpr bool kSurf = (MODE != kRhsVolume);
+  static_assert(64 * (B + 1) <= 4 * J * ROW, "the output rows fit in the staging buffer");
+
+  __shared__ __attribute__((aligned(16))) T stage_buf[4][4 * J * ROW];
 
   // XCD-aware: workgroup b runs on XCD b % 8; each XCD takes a contiguous
-  // eighth of the element range, so neighbour traces stay in its L2
+  // eighth of the workgroups, so neighbouring elements share an L2
   const int64_t per_xcd = (blocks + 7) / 8;
   const int64_t lb = (int64_t)(blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
-  if (lb >= blocks) return;
+  if (lb >= blocks) return;  // whole workgroup: no barrier follows
+  const int w = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
   const int64_t K = A.K;
-  const int64_t e = lb * 256 + threadIdx.x;
-  if (e >= K) return;
+  const int64_t e0 = (lb * 4 + w) * 64;  // the wave's first element
+  if (e0 >= K) return;                   // whole wave
+  T* s = stage_buf[w];
+  const int64_t e = e0 + lane;
+  const bool live = e < K;
   const uint32_t KNp = (uint32_t)(K * Np);
-  const uint32_t base = (uint32_t)e * Np;
 
-  // per-element geometry and flux weights (see kGeoStride)
-  const double* ge = A.geo + e * kGeoStride;
+  // per-element geometry (see kGeoStride)
   T gl[9];
+  T kap = 0;
+  {
+    const double* ge = A.geo + (live ? e : e0) * kGeoStride;
 #pragma unroll
-  for (int i = 0; i < 9; ++i) gl[i] = (T)ge[i];
-  const T kap = (T)ge[9];
-  T ap[4], bu[4];
-  int32_t nb[4];
-  uint32_t info[4];
-#pragma unroll
-  for (int f = 0; f < 4; ++f) {
-    ap[f] = (T)ge[10 + f];
-    bu[f] = (T)ge[14 + f];
-    nb[f] = A.etoe[e * 4 + f];
-    info[f] = A.etofo[e * 4 + f];
+    for (int i = 0; i < 9; ++i) gl[i] = (T)ge[i];
+    kap = (T)ge[9];
   }
-  const T* q0 = A.qin;
-  const T* q1 = A.qin + KNp;
-  const T* q2 = A.qin + 2 * (size_t)KNp;
-  const T* q3 = A.qin + 3 * (size_t)KNp;
 
   for (int blk = 0; blk < NB; ++blk) {
     const int i0 = blk * B;
@@ -86,20 +190,27 @@ __global__ __launch_bounds__(256) void nodal_ept_kernel(NodalArgs<T> A, const T*
 
     if constexpr (kVol) {
       // acc: Dr_1 p, Dr_2 p, Dr_3 p, sum_d Dr_d h_d
+      for (int j0 = 0; j0 < Np; j0 += J) {
+        ept_wave_sync();
+        ept_stage<T>(s, A.qin, KNp, Np, j0, e0, K, lane);
+        ept_wave_sync();
+        const int jn = Np - j0 < J ? Np - j0 : J;
 #pragma unroll 1
-      for (int j = 0; j < Np; ++j) {
-        const T p = q0[base + j], u = q1[base + j], v = q2[base + j], w = q3[base + j];
-        const T h1 = gl[0] * u + gl[1] * v + gl[2] * w;
-        const T h2 = gl[3] * u + gl[4] * v + gl[5] * w;
-        const T h3 = gl[6] * u + gl[7] * v + gl[8] * w;
-        const T* o = opv + ((size_t)j * NpB + i0) * 4;
+        for (int jj = 0; jj < jn; ++jj) {
+          const T p = s[(0 * J + jj) * ROW + lane], u = s[(1 * J + jj) * ROW + lane];
+          const T v = s[(2 * J + jj) * ROW + lane], ww = s[(3 * J + jj) * ROW + lane];
+          const T h1 = gl[0] * u + gl[1] * v + gl[2] * ww;
+          const T h2 = gl[3] * u + gl[4] * v + gl[5] * ww;
+          const T h3 = gl[6] * u + gl[7] * v + gl[8] * ww;
+          const T* o = opv + ((size_t)(j0 + jj) * NpB + i0) * 4;
 #pragma unroll
-        for (int b = 0; b < B; ++b) {
-          const T d1 = o[4 * b], d2 = o[4 * b + 1], d3 = o[4 * b + 2];
-          r[0][b] += d1 * p;
-          r[1][b] += d2 * p;
-          r[2][b] += d3 * p;
-          r[3][b] += d1 * h1 + d2 * h2 + d3 * h3;
+          for (int b = 0; b < B; ++b) {
+            const T d1 = o[4 * b], d2 = o[4 * b + 1], d3 = o[4 * b + 2];
+            r[0][b] += d1 * p;
+            r[1][b] += d2 * p;
+            r[2][b] += d3 * p;
+            r[3][b] += d1 * h1 + d2 * h2 + d3 * h3;
+          }
         }
       }
 #pragma unroll
@@ -113,43 +224,16 @@ __global__ __launch_bounds__(256) void nodal_ept_kernel(NodalArgs<T> A, const T*
     }
 
     if constexpr (kSurf) {
-#pragma unroll
-      for (int f = 0; f < 4; ++f) {
-        // g_f = -2 grad(lambda_f), grad(lambda_0) = -(sum of the others)
-        T gx, gy, gz;
-        if (f == 0) {
-          gx = (T)2 * (gl[0] + gl[3] + gl[6]);
-          gy = (T)2 * (gl[1] + gl[4] + gl[7]);
-          gz = (T)2 * (gl[2] + gl[5] + gl[8]);
-        } else {
-          gx = (T)(-2) * gl[3 * (f - 1)];
-          gy = (T)(-2) * gl[3 * (f - 1) + 1];
-          gz = (T)(-2) * gl[3 * (f - 1) + 2];
-        }
-        const int nbf = nb[f];
-        const uint16_t* perm = t_nbr + ((info[f] & 3) * 6 + (info[f] >> 2)) * Nfp;
-        const uint32_t nbase = nbf >= 0 ? (uint32_t)nbf * Np : 0u;
+      for (int m0 = 0; m0 < NL; m0 += J) {
+        ept_wave_sync();
+        ept_stage<T>(s, F, (size_t)K * NL, NL, m0, e0, K, lane);
+        ept_wave_sync();
+        const int mn = NL - m0 < J ? NL - m0 : J;
 #pragma unroll 1
-        for (int g = 0; g < Nfp; ++g) {
-          const int n = t_fnode[f * Nfp + g];
-          const T pm = q0[base + n], um = q1[base + n], vm = q2[base + n], wm = q3[base + n];
-          const T gum = gx * um + gy * vm + gz * wm;
-          T jp, jgu;
-          if (nbf >= 0) {
-            const uint32_t o = nbase + perm[g];
-            jp = q0[o] - pm;
-            jgu = gx * q1[o] + gy * q2[o] + gz * q3[o] - gum;
-          } else if (A.bc == 0) {  // rigid wall mirror
-            jp = 0;
-            jgu = (T)(-2) * gum;
-          } else {  // pressure-release mirror
-            jp = (T)(-2) * pm;
-            jgu = 0;
-          }
-          const T sp = ap[f] * jp - (T)0.5 * kap * jgu;
-          const T su = bu[f] * jgu - (T)0.5 * jp;
-          const T sx = gx * su, sy = gy * su, sz = gz * su;
-          const T* o = opl + (size_t)(f * Nfp + g) * NpB + i0;
+        for (int jj = 0; jj < mn; ++jj) {
+          const T sp = s[(0 * J + jj) * ROW + lane], sx = s[(1 * J + jj) * ROW + lane];
+          const T sy = s[(2 * J + jj) * ROW + lane], sz = s[(3 * J + jj) * ROW + lane];
+          const T* o = opl + (size_t)(m0 + jj) * NpB + i0;
 #pragma unroll
           for (int b = 0; b < B; ++b) {
             const T l = o[b];
@@ -162,23 +246,28 @@ __global__ __launch_bounds__(256) void nodal_ept_kernel(NodalArgs<T> A, const T*
       }
     }
 
-    // update / store the rows of this block
+    // update / store the rows of this block: each field's B x 64 block goes
+    // through LDS ([element][row], rows of B + 1) so that the global accesses
+    // are coalesced (B consecutive values of one element per B lanes)
+    const int bn = Np - i0 < B ? Np - i0 : B;
 #pragma unroll
-    for (int b = 0; b < B; ++b) {
-      const int i = i0 + b;
-      if (i >= Np) break;
-      const uint32_t off = base + i;
-      if constexpr (MODE == kStage) {
+    for (int fl = 0; fl < 4; ++fl) {
+      ept_wave_sync();
 #pragma unroll
-        for (int fl = 0; fl < 4; ++fl) {
-          const uint32_t o = fl * KNp + off;
-          const T rs = A.dt * r[fl][b] + (A.read_res ? A.rk_a * A.res[o] : (T)0);
+      for (int b = 0; b < B; ++b) s[lane * (B + 1) + b] = r[fl][b];
+      ept_wave_sync();
+      for (int idx = lane; idx < 64 * B; idx += 64) {
+        const int el = idx / B, b = idx % B;
+        if (b >= bn || e0 + el >= K) continue;
+        const uint32_t o = fl * KNp + (uint32_t)(e0 + el) * Np + i0 + b;
+        const T rhs = s[el * (B + 1) + b];
+        if constexpr (MODE == kStage) {
+          const T rs = A.dt * rhs + (A.read_res ? A.rk_a * A.res[o] : (T)0);
           A.res[o] = rs;
           A.qout[o] = A.qin[o] + A.rk_b * rs;
+        } else {
+          A.qout[o] = rhs;
         }
-      } else {
-#pragma unroll
-        for (int fl = 0; fl < 4; ++fl) A.qout[fl * KNp + off] = r[fl][b];
       }
     }
   }
@@ -186,12 +275,22 @@ __global__ __launch_bounds__(256) void nodal_ept_kernel(NodalArgs<T> A, const T*
 
 template <int N, typename T, int MODE>
 static hipError_t ept_launch_one(const NodalArgs<T>& a, hipStream_t stream) {
-  const int64_t blocks = (a.K + 255) / 256;
-  if (blocks <= 0) return hipSuccess;
-  const int64_t grid = (blocks + 7) / 8 * 8;
+  if (a.K <= 0) return hipSuccess;
+  if (!a.flux) return hipErrorInvalidValue;
+  constexpr int NL = 4 * nfp_of(N);
   (void)hipGetLastError();  // drop errors left by earlier, unrelated calls
+  if (MODE != kRhsVolume) {
+    const int64_t items = a.K * NL;
+    int64_t fgrid = (items + 255) / 256;
+    if (fgrid > 65536) fgrid = 65536;
+    hipLaunchKernelGGL((ept_flux_kernel<N, T>), dim3((unsigned)fgrid), dim3(256), 0, stream, a, a.flux);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  const int64_t blocks = (a.K + 255) / 256;  // four waves of 64 elements
+  const int64_t grid = (blocks + 7) / 8 * 8;
   hipLaunchKernelGGL((nodal_ept_kernel<N, T, MODE>), dim3((unsigned)grid), dim3(256), 0, stream, a, a.dr, a.lift,
-                     blocks);
+                     (const T*)a.flux, blocks);
   return hipGetLastError();
 }
 
