@@ -9,14 +9,31 @@
 //   LIFT = [V E_L^f L_0 Vf^{-1}]_f         -> lifted flux of the four faces
 // with V (Vf) the Bernstein-Vandermonde matrix of the volume (face) lattice.
 //
-// Each wave owns blocks of 4 elements = 16 columns (element-major, field
-// fastest); waves of a workgroup are independent after loading the tables.  The volume term is three MFMA GEMMs (NpP x Kv) x (Kv x 16), the
-// surface term one MFMA GEMM (NpP x Kl) x (Kl x 16) on the face-node fluxes
-// (the p flux and the velocity flux scaled by the three components of g_f),
-// followed by the fused LSRK4 update.  MFMA tiles are 16 x 16 x 4
-// (v_mfma_f64_16x16x4f64 / v_mfma_f32_16x16x4f32); lane l holds A[l%16][l/16]
-// and B[l/16][l%16]; accumulator register r of lane l is D[row][l%16] with
-// row = l/16 + 4r for the FP64 instruction and 4(l/16) + r for the FP32 one.
+// A workgroup of four waves takes a block of EB elements, NC = 4 EB columns
+// (element-major, field fastest), and computes the block's right-hand side
+// as MFMA GEMMs whose B operands sit in LDS, laid out k-major ([k][column],
+// rows padded to NC + 16 so that the 16 x 4 operand reads are free of bank
+// conflicts), and whose A operands (the operators, shared by every block)
+// come from L1/L2; every A tile a wave loads feeds the MFMAs of its column
+// tiles.  The waves split the 16-row tiles of the output (and, where there
+// are fewer row tiles than waves, the column tiles).
+//   1. Stage the block's nodal values X (Kv x NC) in LDS.
+//   2. Volume: for i = 1..3, Y_i = Dr_i X by MFMA, then the geometric
+//      combination in registers: the four columns of an element are four
+//      neighbouring lanes of the accumulator, so rhs_p = -kappa sum_i
+//      grad(lambda_i).(Y_i u, Y_i v, Y_i w) and rhs_u = -sum_i grad(lambda_i)
+//      Y_i p are quad reductions and broadcasts (DPP).
+//   3. The upwind flux of every face node (own traces from X, the
+//      neighbour's from global memory) goes to registers; once every wave is
+//      done with X the fluxes (sp, g su) replace it in LDS as the B operand
+//      of the lift (Kl x NC), and rhs += LIFT F is accumulated on the same
+//      registers.
+//   4. The fused LSRK4 update reads and writes the fields from the
+//      accumulator layout.
+// MFMA tiles are 16 x 16 x 4 (v_mfma_f64_16x16x4f64 / v_mfma_f32_16x16x4f32);
+// lane l holds A[l%16][l/16] and B[l/16][l%16]; accumulator register r of
+// lane l is D[row][l%16] with row = l/16 + 4r for the FP64 instruction and
+// 4(l/16) + r for the FP32 one.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -26,12 +43,6 @@
 namespace bbdg {
 
 namespace {
-
-__device__ __forceinline__ void wave_sync_lds() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-}
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -57,226 +68,253 @@ struct Mfma<float> {
   static __device__ __forceinline__ int row(int kq, int r) { return 4 * kq + r; }
 };
 
+// Lane permutations within groups of four lanes (DPP quad_perm).
+template <int CTRL>
+__device__ __forceinline__ float quad_perm(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double quad_perm(double x) {
+  const long long v = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(v & 0xffffffffLL), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(v >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+constexpr int kQuadBcast0 = 0x00;  // every lane of the quad reads lane 0
+constexpr int kQuadSwap1 = 0xB1;   // (1, 0, 3, 2)
+constexpr int kQuadSwap2 = 0x4E;   // (2, 3, 0, 1)
+
 }  // namespace
 
-// Waves per workgroup: bounded by the two per-wave LDS buffers.
+#ifndef BBDG_NODAL_EB_F64
+#define BBDG_NODAL_EB_F64(N) ((N) <= 4 ? 16 : ((N) == 5 ? 12 : ((N) <= 7 ? 8 : 4)))
+#endif
+#ifndef BBDG_NODAL_EB_F32
+#define BBDG_NODAL_EB_F32(N) ((N) <= 6 ? 16 : 8)
+#endif
+
+// Block shape of order N: EB elements per workgroup (NC = 4 EB columns, CT
+// column tiles of 16), LDS rows of NCP values, MT row tiles.  The four waves
+// form WR groups along the rows and WC = 4 / WR along the columns (fewer row
+// tiles than waves at low order): a wave takes at most RPW row tiles and CTW
+// column tiles.  NIT face-node items per thread for the flux.
 template <int N, typename T>
-struct NodalWaves {
-  static constexpr int value = sizeof(T) == 8 ? (N <= 5 ? 4 : (N <= 7 ? 2 : 1)) : (N <= 7 ? 4 : 2);
+struct NodalCfg {
+  static constexpr int Np = np_of(N), Nfp = nfp_of(N), NL = 4 * nfp_of(N);
+  static constexpr NodalDims D = nodal_dims(N);
+  static constexpr int NpP = D.NpP, Kv = D.Kv, Kl = D.Kl;
+  static constexpr int KMAX = Kv > Kl ? Kv : Kl;
+  static constexpr int EB = sizeof(T) == 8 ? BBDG_NODAL_EB_F64(N) : BBDG_NODAL_EB_F32(N);
+  static constexpr int NC = 4 * EB, CT = NC / 16, NCP = NC + 16;
+  static constexpr int MT = NpP / 16;
+  static constexpr int WR = MT >= 4 ? 4 : (MT >= 2 ? 2 : 1), WC = 4 / WR;
+  static constexpr int RPW = (MT + WR - 1) / WR, CTW = CT / WC > 0 ? CT / WC : 1;
+  static constexpr int NIT = (EB * NL + 255) / 256;
+  static_assert(CT % WC == 0 || CT < WC, "column tiles split evenly over the column groups");
 };
 
 template <int N, typename T, int MODE>
-__global__ __launch_bounds__((64 * NodalWaves<N, T>::value)) void nodal_stage_kernel(NodalArgs<T> A) {
-  constexpr int Np = np_of(N), Nfp = nfp_of(N);
-  constexpr NodalDims D = nodal_dims(N);
-  constexpr int NpP = D.NpP, Kv = D.Kv, Kl = D.Kl;
-  constexpr int EB = 4, NC = 16;  // elements per block, columns per block
-  constexpr int WPB = NodalWaves<N, T>::value;
-  // bx: volume B operand X[col][k] (also read for own face traces), later the
-  //     lift output [row][col]; by: volume outputs [row][col], later the flux
-  //     block F[k][col] (the B operand of the lift)
-  constexpr int SZX = (NC * Kv > NpP * NC) ? NC * Kv : NpP * NC;
-  constexpr int SZY = (NpP > Kl ? NpP : Kl) * NC;
-  constexpr int NIT = (EB * Np + 63) / 64;  // (node, element) items per lane
-  constexpr int NFI = (EB * 4 * Nfp + 63) / 64;
-  constexpr bool kVol = (MODE != kRhsSurface);
-  constexpr bool kSurf = (MODE != kRhsVolume);
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void nodal_stage_kernel(NodalArgs<T> A,
+                                                                                            int64_t blocks) {
+  using C = NodalCfg<N, T>;
   using M = Mfma<T>;
   typedef typename M::acc acc_t;
+  constexpr int Np = C::Np, Nfp = C::Nfp, NL = C::NL, Kv = C::Kv, Kl = C::Kl, NpP = C::NpP;
+  constexpr int EB = C::EB, NC = C::NC, CT = C::CT, NCP = C::NCP, MT = C::MT, RPW = C::RPW, NIT = C::NIT;
+  constexpr int WR = C::WR, CTW = C::CTW;
+  constexpr bool kVol = (MODE != kRhsSurface);
+  constexpr bool kSurf = (MODE != kRhsVolume);
+  constexpr TabLayout L = tab_layout(N);
 
+  __shared__ __attribute__((aligned(16))) T buf[C::KMAX * NCP];
+  __shared__ double shg[EB * kGeoStride];
+  __shared__ int32_t she[EB * 4];
+  __shared__ uint8_t shf[EB * 4];
   __shared__ uint16_t t_nbr[24 * Nfp];
   __shared__ uint16_t t_fnode[4 * Nfp];
-  __shared__ __attribute__((aligned(16))) T bx[WPB][SZX];
-  __shared__ __attribute__((aligned(16))) T by[WPB][SZY];
-  __shared__ double shg[WPB][EB * kGeoStride];
-  __shared__ int32_t she[WPB][EB * 4];
-  __shared__ uint8_t shf[WPB][EB * 4];
 
+  // XCD-aware: workgroup b runs on XCD b % 8, which takes a contiguous
+  // eighth of the element blocks (neighbour traces then share its L2)
+  const int64_t per_xcd = (blocks + 7) / 8;
+  const int64_t lb = (int64_t)(blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+  if (lb >= blocks) return;  // the whole workgroup
   const int tid = threadIdx.x;
-  const TabLayout L = tab_layout(N);
-  for (int i = tid; i < 24 * Nfp; i += 64 * WPB) t_nbr[i] = A.tab[L.nbrnode + i];
-  for (int i = tid; i < 4 * Nfp; i += 64 * WPB) t_fnode[i] = A.tab[L.fnode + i];
+  const int64_t K = A.K;
+  const uint32_t KNp = (uint32_t)(K * Np);
+  const int64_t e0 = lb * EB;
+
+  for (int i = tid; i < 24 * Nfp; i += 256) t_nbr[i] = A.tab[L.nbrnode + i];
+  for (int i = tid; i < 4 * Nfp; i += 256) t_fnode[i] = A.tab[L.fnode + i];
+  for (int v = tid; v < EB * kGeoStride; v += 256) {
+    const int64_t idx = e0 * kGeoStride + v;
+    shg[v] = idx < K * kGeoStride ? A.geo[idx] : 0.0;
+  }
+  if (tid < EB * 4) {
+    const int64_t idx = e0 * 4 + tid;
+    she[tid] = idx < K * 4 ? A.etoe[idx] : -1;
+    shf[tid] = idx < K * 4 ? A.etofo[idx] : 0;
+  }
+  // X: buf[k][col] = field (col % 4) of element e0 + col / 4 at node k
+  for (int idx = tid; idx < Kv * NC; idx += 256) {
+    const int k = idx / NC, col = idx - k * NC;
+    const int el = col >> 2, fl = col & 3;
+    T v = 0;
+    if (k < Np && e0 + el < K) v = A.qin[fl * KNp + (uint32_t)(e0 + el) * Np + k];
+    buf[k * NCP + col] = v;
+  }
   __syncthreads();
-  T* const xs = bx[tid >> 6];  // X[col][k] = xs[col * Kv + k]; lift output [row][col] = xs[row * NC + col]
-  T* const ys = by[tid >> 6];  // Y[row][col] = ys[row * NC + col]; F[k][col] = ys[k * NC + col]
 
-  const int lane0 = tid & 63, w = tid >> 6;
-  const int64_t K = A.K, KNp = K * Np;
-  const int64_t G = (K + EB - 1) / EB;
-  const int xcd = blockIdx.x & 7;
-  const int64_t g_lo = G * xcd / 8, g_hi = G * (xcd + 1) / 8;
-  const int64_t wstride = (int64_t)(gridDim.x >> 3) * WPB;
+  const int w = tid >> 6, lane = tid & 63;
+  const int ri = lane & 15;  // MFMA row / column index within a tile
+  const int kq = lane >> 4;  // MFMA k index (0..3) / accumulator row block
+  const int fl = ri & 3;     // field of this lane's columns
+  const int wr = w % WR;     // this wave's row group: row tiles wr, wr + WR, ...
+  const int c0 = (w / WR) * CTW;  // and its first column tile
+  const bool cols = c0 < CT;      // (no columns for this wave when CT < WC)
 
-  for (int64_t g = g_lo + (int64_t)(blockIdx.x >> 3) * WPB + w; g < g_hi; g += wstride) {
-    int lane = lane0;
-    asm volatile("" : "+v"(lane));
-    const int64_t e0 = g * EB;
-    const int ri = lane & 15;  // MFMA row / column index within a tile
-    const int kq = lane >> 4;  // MFMA k index (0..3) / accumulator row block
+  acc_t rhs[RPW][CTW];
+#pragma unroll
+  for (int r = 0; r < RPW; ++r)
+#pragma unroll
+    for (int ct = 0; ct < CTW; ++ct) rhs[r][ct] = M::zero();
 
-    // ---- header, own coefficients -------------------------------------------
-    wave_sync_lds();
-    for (int v = lane; v < EB * kGeoStride; v += 64) {
-      const int64_t idx = e0 * kGeoStride + v;
-      shg[w][v] = idx < K * kGeoStride ? A.geo[idx] : 0.0;
-    }
-    if (lane < EB * 4) {
-      const int64_t idx = e0 * 4 + lane;
-      she[w][lane] = idx < K * 4 ? A.etoe[idx] : -1;
-      shf[w][lane] = idx < K * 4 ? A.etofo[idx] : 0;
-    }
-    T qv[NIT][4];
+  // ---- volume: Y_i = Dr_i X, combined with grad(lambda_i) per element ---------------
+  if constexpr (kVol) {
 #pragma unroll
-    for (int r = 0; r < NIT; ++r) {
-      const int v = lane + 64 * r;
-      const int el = v / Np, n = v - el * Np;
-      const bool ok = v < EB * Np && e0 + el < K;
-      const int64_t off = ok ? (e0 + el) * Np + n : 0;
-#pragma unroll
-      for (int f = 0; f < 4; ++f) qv[r][f] = ok ? A.qin[f * KNp + off] : (T)0;
-    }
-    // volume B operand: xs[col][k], col = 4 el + field, zero padding for k >= Np
-    for (int v = lane; v < NC * Kv; v += 64) xs[v] = 0;
-    wave_sync_lds();
-#pragma unroll
-    for (int r = 0; r < NIT; ++r) {
-      const int v = lane + 64 * r;
-      if (v < EB * Np) {
-        const int el = v / Np, n = v - el * Np;
-#pragma unroll
-        for (int f = 0; f < 4; ++f) xs[(4 * el + f) * Kv + n] = qv[r][f];
-      }
-    }
-    wave_sync_lds();
-
-    T rhs[NIT][4];
-#pragma unroll
-    for (int r = 0; r < NIT; ++r)
-#pragma unroll
-      for (int f = 0; f < 4; ++f) rhs[r][f] = 0;
-
-    // ---- volume: Y_i = Dr_i X, combined with grad(lambda_i) per element ------
-    if constexpr (kVol) {
+    for (int r = 0; r < RPW; ++r) {
+      const int rt = wr + WR * r;
+      if (rt >= MT || !cols) break;
+#pragma unroll 1
       for (int i = 0; i < 3; ++i) {
-        const T* Di = A.dr + (size_t)i * NpP * Kv;
-        for (int mt = 0; mt < NpP / 16; ++mt) {
-          acc_t c = M::zero();
+        acc_t y[CTW];
+#pragma unroll
+        for (int ct = 0; ct < CTW; ++ct) y[ct] = M::zero();
+        const T* Ai = A.dr + (size_t)i * NpP * Kv + (size_t)(rt * 16 + ri) * Kv + kq;
 #pragma unroll 4
-          for (int k0 = 0; k0 < Kv; k0 += 4) {
-            const T a = Di[(mt * 16 + ri) * Kv + k0 + kq];
-            const T b = xs[ri * Kv + k0 + kq];
-            c = M::mac(a, b, c);
+        for (int k0 = 0; k0 < Kv; k0 += 4) {
+          const T a = Ai[k0];
+#pragma unroll
+          for (int ct = 0; ct < CTW; ++ct)
+            y[ct] = M::mac(a, buf[(k0 + kq) * NCP + (c0 + ct) * 16 + ri], y[ct]);
+        }
+#pragma unroll
+        for (int ct = 0; ct < CTW; ++ct) {
+          const int el = (c0 + ct) * 4 + (ri >> 2);
+          // d(lambda_{i+1})/d(x_{fl-1}) on velocity lanes, 0 on pressure lanes
+          const T gc = fl ? (T)shg[el * kGeoStride + 3 * i + fl - 1] : (T)0;
+          const T kap = (T)shg[el * kGeoStride + 9];
+#pragma unroll
+          for (int rr = 0; rr < 4; ++rr) {
+            const T yv = y[ct][rr];
+            const T p = quad_perm<kQuadBcast0>(yv);
+            T s = gc * yv;
+            s += quad_perm<kQuadSwap1>(s);
+            s += quad_perm<kQuadSwap2>(s);
+            rhs[r][ct][rr] -= fl ? gc * p : kap * s;
           }
-#pragma unroll
-          for (int rr = 0; rr < 4; ++rr) ys[(mt * 16 + M::row(kq, rr)) * NC + ri] = c[rr];
         }
-        wave_sync_lds();
-#pragma unroll
-        for (int r = 0; r < NIT; ++r) {
-          const int v = lane + 64 * r;
-          if (v >= EB * Np) continue;
-          const int el = v / Np, n = v - el * Np;
-          const double* ge = shg[w] + el * kGeoStride;
-          const T gx = (T)ge[3 * i], gy = (T)ge[3 * i + 1], gz = (T)ge[3 * i + 2];
-          const T kap = (T)ge[9];
-          const T* y = ys + n * NC + 4 * el;
-          rhs[r][0] -= kap * (gx * y[1] + gy * y[2] + gz * y[3]);
-          rhs[r][1] -= gx * y[0];
-          rhs[r][2] -= gy * y[0];
-          rhs[r][3] -= gz * y[0];
-        }
-        wave_sync_lds();
       }
     }
+  }
 
-    // ---- surface: flux on face nodes, then R = LIFT F ---------------------------
-    if constexpr (kSurf) {
-      for (int v = lane; v < Kl * NC; v += 64) ys[v] = 0;
-      wave_sync_lds();
+  // ---- upwind flux of every face node of the block, into registers ----------------
+  T fv[kSurf ? NIT : 1][4];
+  if constexpr (kSurf) {
 #pragma unroll
-      for (int r = 0; r < NFI; ++r) {
-        const int v = lane + 64 * r;
-        const int el = v / (4 * Nfp);
-        const int rem = v - el * 4 * Nfp;
-        const int f = rem / Nfp, gg = rem - f * Nfp;
-        if (v >= EB * 4 * Nfp || e0 + el >= K) continue;
-        const int n = t_fnode[f * Nfp + gg];
-        const T pm = xs[(4 * el) * Kv + n], um = xs[(4 * el + 1) * Kv + n], vm = xs[(4 * el + 2) * Kv + n],
-                wm = xs[(4 * el + 3) * Kv + n];
-        const double* ge = shg[w] + el * kGeoStride;
-        double lx, ly, lz;  // grad lambda_f
-        if (f == 0) {
-          lx = -(ge[0] + ge[3] + ge[6]);
-          ly = -(ge[1] + ge[4] + ge[7]);
-          lz = -(ge[2] + ge[5] + ge[8]);
-        } else {
-          lx = ge[3 * (f - 1)];
-          ly = ge[3 * (f - 1) + 1];
-          lz = ge[3 * (f - 1) + 2];
-        }
-        const T gx = (T)(-2.0 * lx), gy = (T)(-2.0 * ly), gz = (T)(-2.0 * lz);
-        const int nb = she[w][el * 4 + f];
-        T jp, jgu;
-        if (nb >= 0) {
-          const int info = shf[w][el * 4 + f];
-          const int64_t off = (int64_t)nb * Np + t_nbr[((info & 3) * 6 + (info >> 2)) * Nfp + gg];
-          jp = A.qin[off] - pm;
-          jgu = gx * (A.qin[KNp + off] - um) + gy * (A.qin[2 * KNp + off] - vm) + gz * (A.qin[3 * KNp + off] - wm);
-        } else if (A.bc == 0) {
-          jp = 0;
-          jgu = (T)(-2) * (gx * um + gy * vm + gz * wm);
-        } else {
-          jp = (T)(-2) * pm;
-          jgu = 0;
-        }
-        const T sp = (T)ge[10 + f] * jp - (T)(0.5 * ge[9]) * jgu;
-        const T su = (T)ge[14 + f] * jgu - (T)0.5 * jp;
-        T* col = ys + (f * Nfp + gg) * NC + 4 * el;
-        col[0] = sp;
-        col[1] = gx * su;
-        col[2] = gy * su;
-        col[3] = gz * su;
-      }
-      wave_sync_lds();
-      for (int mt = 0; mt < NpP / 16; ++mt) {
-        acc_t c = M::zero();
-#pragma unroll 4
-        for (int k0 = 0; k0 < Kl; k0 += 4) {
-          const T a = A.lift[(mt * 16 + ri) * Kl + k0 + kq];
-          const T b = ys[(k0 + kq) * NC + ri];
-          c = M::mac(a, b, c);
-        }
-#pragma unroll
-        for (int rr = 0; rr < 4; ++rr) xs[(mt * 16 + M::row(kq, rr)) * NC + ri] = c[rr];
-      }
-      wave_sync_lds();
-#pragma unroll
-      for (int r = 0; r < NIT; ++r) {
-        const int v = lane + 64 * r;
-        if (v >= EB * Np) continue;
-        const int el = v / Np, n = v - el * Np;
-#pragma unroll
-        for (int f = 0; f < 4; ++f) rhs[r][f] += xs[n * NC + 4 * el + f];
-      }
-    }
-
-    // ---- update / store ------------------------------------------------------------
-#pragma unroll
-    for (int r = 0; r < NIT; ++r) {
-      const int v = lane + 64 * r;
-      const int el = v / Np, n = v - el * Np;
-      if (v >= EB * Np || e0 + el >= K) continue;
-      const int64_t off = (e0 + el) * Np + n;
-      if constexpr (MODE == kStage) {
-#pragma unroll
-        for (int f = 0; f < 4; ++f) {
-          const T rs = A.dt * rhs[r][f] + (A.read_res ? A.rk_a * A.res[f * KNp + off] : (T)0);
-          A.res[f * KNp + off] = rs;
-          A.qout[f * KNp + off] = qv[r][f] + A.rk_b * rs;
-        }
+    for (int j = 0; j < NIT; ++j) {
+      const int it = tid + 256 * j;
+      const int el = it / NL, m = it - el * NL;
+      fv[j][0] = fv[j][1] = fv[j][2] = fv[j][3] = 0;
+      if (it >= EB * NL || e0 + el >= K) continue;
+      const int f = m / Nfp, g = m - f * Nfp;
+      const int n = t_fnode[m];
+      const T pm = buf[n * NCP + 4 * el], um = buf[n * NCP + 4 * el + 1], vm = buf[n * NCP + 4 * el + 2],
+              wm = buf[n * NCP + 4 * el + 3];
+      const double* ge = shg + el * kGeoStride;
+      double lx, ly, lz;  // grad lambda_f
+      if (f == 0) {
+        lx = -(ge[0] + ge[3] + ge[6]);
+        ly = -(ge[1] + ge[4] + ge[7]);
+        lz = -(ge[2] + ge[5] + ge[8]);
       } else {
+        lx = ge[3 * (f - 1)];
+        ly = ge[3 * (f - 1) + 1];
+        lz = ge[3 * (f - 1) + 2];
+      }
+      const T gx = (T)(-2.0 * lx), gy = (T)(-2.0 * ly), gz = (T)(-2.0 * lz);
+      const T gum = gx * um + gy * vm + gz * wm;
+      const int nb = she[el * 4 + f];
+      T jp, jgu;
+      if (nb >= 0) {
+        const int info = shf[el * 4 + f];
+        const uint32_t o = (uint32_t)nb * Np + t_nbr[((info & 3) * 6 + (info >> 2)) * Nfp + g];
+        jp = A.qin[o] - pm;
+        jgu = gx * A.qin[KNp + o] + gy * A.qin[2 * KNp + o] + gz * A.qin[3 * KNp + o] - gum;
+      } else if (A.bc == 0) {  // rigid wall mirror
+        jp = 0;
+        jgu = (T)(-2) * gum;
+      } else {  // pressure-release mirror
+        jp = (T)(-2) * pm;
+        jgu = 0;
+      }
+      const T sp = (T)ge[10 + f] * jp - (T)(0.5 * ge[9]) * jgu;
+      const T su = (T)ge[14 + f] * jgu - (T)0.5 * jp;
+      fv[j][0] = sp;
+      fv[j][1] = gx * su;
+      fv[j][2] = gy * su;
+      fv[j][3] = gz * su;
+    }
+  }
+
+  // ---- surface: the fluxes replace X in LDS, rhs += LIFT F ---------------------------
+  if constexpr (kSurf) {
+    __syncthreads();  // every wave is done with X
 #pragma unroll
-        for (int f = 0; f < 4; ++f) A.qout[f * KNp + off] = rhs[r][f];
+    for (int j = 0; j < NIT; ++j) {
+      const int it = tid + 256 * j;
+      if (it >= EB * NL) continue;
+      const int el = it / NL, m = it - el * NL;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) buf[m * NCP + 4 * el + c] = fv[j][c];
+    }
+    for (int idx = tid; idx < (Kl - NL) * NC; idx += 256) buf[(NL + idx / NC) * NCP + idx % NC] = 0;
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) {
+      const int rt = wr + WR * r;
+      if (rt >= MT || !cols) break;
+      const T* Lr = A.lift + (size_t)(rt * 16 + ri) * Kl + kq;
+#pragma unroll 4
+      for (int k0 = 0; k0 < Kl; k0 += 4) {
+        const T a = Lr[k0];
+#pragma unroll
+        for (int ct = 0; ct < CTW; ++ct)
+          rhs[r][ct] = M::mac(a, buf[(k0 + kq) * NCP + (c0 + ct) * 16 + ri], rhs[r][ct]);
+      }
+    }
+  }
+
+  // ---- update / store from the accumulator layout -----------------------------------------
+#pragma unroll
+  for (int r = 0; r < RPW; ++r) {
+    const int rt = wr + WR * r;
+    if (rt >= MT || !cols) break;
+#pragma unroll
+    for (int ct = 0; ct < CTW; ++ct) {
+      const int64_t e = e0 + (c0 + ct) * 4 + (ri >> 2);
+      if (e >= K) continue;
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) {
+        const int row = rt * 16 + M::row(kq, rr);
+        if (row >= Np) continue;
+        const uint32_t o = fl * KNp + (uint32_t)e * Np + row;
+        if constexpr (MODE == kStage) {
+          const T rs = A.dt * rhs[r][ct][rr] + (A.read_res ? A.rk_a * A.res[o] : (T)0);
+          A.res[o] = rs;
+          A.qout[o] = A.qin[o] + A.rk_b * rs;
+        } else {
+          A.qout[o] = rhs[r][ct][rr];
+        }
       }
     }
   }
@@ -284,26 +322,12 @@ __global__ __launch_bounds__((64 * NodalWaves<N, T>::value)) void nodal_stage_ke
 
 template <int N, typename T, int MODE>
 static hipError_t nodal_launch_one(const NodalArgs<T>& a, hipStream_t stream) {
-  constexpr int WPB = NodalWaves<N, T>::value;
-  const int64_t groups = (a.K + 3) / 4;
-  if (groups <= 0) return hipSuccess;
-  static int resident = 0, cus = 0;
-  if (resident == 0) {
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return hipErrorInvalidDevice;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return hipErrorInvalidDevice;
-    int occ = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, nodal_stage_kernel<N, T, MODE>, 64 * WPB, 0) != hipSuccess)
-      return hipErrorInvalidValue;
-    resident = occ > 0 ? occ : 1;
-  }
-  const int64_t needed = (groups + WPB - 1) / WPB;
-  int64_t grid = (int64_t)resident * cus;
-  if (grid > ((needed + 7) / 8) * 8) grid = ((needed + 7) / 8) * 8;
-  grid = ((grid + 7) / 8) * 8;
-  if (grid < 8) grid = 8;
+  using C = NodalCfg<N, T>;
+  const int64_t blocks = (a.K + C::EB - 1) / C::EB;
+  if (blocks <= 0) return hipSuccess;
+  const int64_t grid = (blocks + 7) / 8 * 8;
   (void)hipGetLastError();  // drop errors left by earlier, unrelated calls
-  hipLaunchKernelGGL((nodal_stage_kernel<N, T, MODE>), dim3((unsigned)grid), dim3(64 * WPB), 0, stream, a);
+  hipLaunchKernelGGL((nodal_stage_kernel<N, T, MODE>), dim3((unsigned)grid), dim3(256), 0, stream, a, blocks);
   return hipGetLastError();
 }
 
