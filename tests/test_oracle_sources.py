@@ -149,3 +149,21 @@ def test_pins_catch_a_wrong_stage_time(monkeypatch):
     out, _ = prob.run_shots(q0, dt, steps, elem, lam, F0, TS, [], np.zeros((0, 4)), t0=t0)
     exact = _ricker_antiderivative(t0 + steps * dt) - _ricker_antiderivative(t0)
     assert abs(prob.pressure_integral(out[0]) - exact) > 1e-6
+
+
+def test_resume_is_bitwise():
+    """A forced oracle run of 10 steps equals 4 steps followed by 6 steps from
+    t0 + 4 dt, bit for bit (dt a power of two keeps the stage times exact),
+    states and traces."""
+    prob = _problem(N=2)
+    rng = np.random.default_rng(9)
+    elem, lam = prob.locate(rng.uniform(0.1, 0.9, (2, 3)))
+    relem, rlam = prob.locate(rng.uniform(0.1, 0.9, (3, 3)))
+    q0 = np.zeros((2, 4, prob.K, prob.Np))
+    dt, t0 = 2.0 ** -10, 0.0625
+    qa, ta = prob.run_shots(q0, dt, 10, elem, lam, F0, TS, relem, rlam, t0=t0)
+    q1, t1 = prob.run_shots(q0, dt, 4, elem, lam, F0, TS, relem, rlam, t0=t0)
+    qb, t2 = prob.run_shots(q1, dt, 6, elem, lam, F0, TS, relem, rlam, t0=t0 + 4 * dt)
+    np.testing.assert_array_equal(qa, qb)
+    np.testing.assert_array_equal(ta, np.concatenate([t1, t2]))
+    assert np.abs(qa).max() > 0
