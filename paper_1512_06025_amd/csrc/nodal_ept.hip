@@ -4,9 +4,9 @@
 // thread owns one element and applies the dense derivative and lift matrices
 // to it in blocks of output rows, the operator entries of a block being
 // shared by all threads, so that each entry fetched is reused by a whole
-// wavefront of elements.  Here the entries are wave-uniform scalar loads
-// (SGPR operands of v_fma, through the scalar cache) instead of blocks staged
-// in shared memory, and the 64 lanes of a wave are 64 consecutive elements.
+// workgroup of elements: here 256 consecutive elements (four waves of 64), the
+// operator tile of the current row block and input chunk staged in LDS and
+// read with wave-uniform (broadcast) addresses.
 // As in the paper the surface work is split: a flux kernel writes the upwind
 // flux of every face node to a buffer, and the element-per-thread kernel
 // applies the derivative matrices, the lift and the LSRK4 update.  The scheme
@@ -156,17 +156,22 @@ __global__ __launch_bounds__(256) void nodal_ept_kernel(NodalArgs<T> A, const T*
   static_assert(64 * (B + 1) <= 4 * J * ROW, "the output rows fit in the staging buffer");
 
   __shared__ __attribute__((aligned(16))) T stage_buf[4][4 * J * ROW];
+  // operator tile of the current row block and chunk, shared by the four
+  // waves: (Dr_1, Dr_2, Dr_3, 0) of B rows for J inputs, or LIFT of B rows
+  // for J face nodes
+  __shared__ __attribute__((aligned(16))) T op_tile[J * B * 4];
 
   // XCD-aware: workgroup b runs on XCD b % 8; each XCD takes a contiguous
   // eighth of the workgroups, so neighbouring elements share an L2
   const int64_t per_xcd = (blocks + 7) / 8;
   const int64_t lb = (int64_t)(blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
   if (lb >= blocks) return;  // whole workgroup: no barrier follows
-  const int w = threadIdx.x >> 6;
-  const int lane = threadIdx.x & 63;
+  const int tid = threadIdx.x;
+  const int w = tid >> 6;
+  const int lane = tid & 63;
   const int64_t K = A.K;
-  const int64_t e0 = (lb * 4 + w) * 64;  // the wave's first element
-  if (e0 >= K) return;                   // whole wave
+  const int64_t e0 = (lb * 4 + w) * 64;  // the wave's first element (may lie past K: the wave
+                                         // still takes part in the workgroup's barriers)
   T* s = stage_buf[w];
   const int64_t e = e0 + lane;
   const bool live = e < K;
@@ -176,7 +181,7 @@ __global__ __launch_bounds__(256) void nodal_ept_kernel(NodalArgs<T> A, const T*
   T gl[9];
   T kap = 0;
   {
-    const double* ge = A.geo + (live ? e : e0) * kGeoStride;
+    const double* ge = A.geo + (live ? e : 0) * kGeoStride;
 #pragma unroll
     for (int i = 0; i < 9; ++i) gl[i] = (T)ge[i];
     kap = (T)ge[9];
@@ -191,10 +196,14 @@ __global__ __launch_bounds__(256) void nodal_ept_kernel(NodalArgs<T> A, const T*
     if constexpr (kVol) {
       // acc: Dr_1 p, Dr_2 p, Dr_3 p, sum_d Dr_d h_d
       for (int j0 = 0; j0 < Np; j0 += J) {
-        ept_wave_sync();
-        ept_stage<T>(s, A.qin, KNp, Np, j0, e0, K, lane);
-        ept_wave_sync();
         const int jn = Np - j0 < J ? Np - j0 : J;
+        __syncthreads();  // the previous chunk's tile and buffers are consumed
+        ept_stage<T>(s, A.qin, KNp, Np, j0, e0, K, lane);
+        for (int t = tid; t < jn * B * 4; t += 256) {
+          const int jj = t / (B * 4), rest = t - jj * (B * 4);
+          op_tile[t] = opv[((size_t)(j0 + jj) * NpB + i0) * 4 + rest];
+        }
+        __syncthreads();
 #pragma unroll 1
         for (int jj = 0; jj < jn; ++jj) {
           const T p = s[(0 * J + jj) * ROW + lane], u = s[(1 * J + jj) * ROW + lane];
@@ -202,7 +211,7 @@ __global__ __launch_bounds__(256) void nodal_ept_kernel(NodalArgs<T> A, const T*
           const T h1 = gl[0] * u + gl[1] * v + gl[2] * ww;
           const T h2 = gl[3] * u + gl[4] * v + gl[5] * ww;
           const T h3 = gl[6] * u + gl[7] * v + gl[8] * ww;
-          const T* o = opv + ((size_t)(j0 + jj) * NpB + i0) * 4;
+          const T* o = op_tile + jj * B * 4;
 #pragma unroll
           for (int b = 0; b < B; ++b) {
             const T d1 = o[4 * b], d2 = o[4 * b + 1], d3 = o[4 * b + 2];
@@ -225,15 +234,19 @@ __global__ __launch_bounds__(256) void nodal_ept_kernel(NodalArgs<T> A, const T*
 
     if constexpr (kSurf) {
       for (int m0 = 0; m0 < NL; m0 += J) {
-        ept_wave_sync();
-        ept_stage<T>(s, F, (size_t)K * NL, NL, m0, e0, K, lane);
-        ept_wave_sync();
         const int mn = NL - m0 < J ? NL - m0 : J;
+        __syncthreads();
+        ept_stage<T>(s, F, (size_t)K * NL, NL, m0, e0, K, lane);
+        for (int t = tid; t < mn * B; t += 256) {
+          const int jj = t / B, b = t - jj * B;
+          op_tile[t] = opl[(size_t)(m0 + jj) * NpB + i0 + b];
+        }
+        __syncthreads();
 #pragma unroll 1
         for (int jj = 0; jj < mn; ++jj) {
           const T sp = s[(0 * J + jj) * ROW + lane], sx = s[(1 * J + jj) * ROW + lane];
           const T sy = s[(2 * J + jj) * ROW + lane], sz = s[(3 * J + jj) * ROW + lane];
-          const T* o = opl + (size_t)(m0 + jj) * NpB + i0;
+          const T* o = op_tile + jj * B;
 #pragma unroll
           for (int b = 0; b < B; ++b) {
             const T l = o[b];
@@ -252,7 +265,7 @@ __global__ __launch_bounds__(256) void nodal_ept_kernel(NodalArgs<T> A, const T*
     const int bn = Np - i0 < B ? Np - i0 : B;
 #pragma unroll
     for (int fl = 0; fl < 4; ++fl) {
-      ept_wave_sync();
+      ept_wave_sync();  // the wave's own buffer: no workgroup barrier needed
 #pragma unroll
       for (int b = 0; b < B; ++b) s[lane * (B + 1) + b] = r[fl][b];
       ept_wave_sync();
