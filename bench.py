@@ -545,7 +545,9 @@ def main():
                                          cfg1["steps"], 0, "f64")
             gpu_stage_s["c1"] = m1 * 1e-3 / (5 * cfg1["steps"])
         headline_is_c2 = args.config == "c2" and args.order is None
-        out["cpu_baseline"] = cpu_baseline(workload, q0 if headline_is_c2 else None, gpu_stage_s)
+        # the oracle takes (4, K, Np) states; q0 is in the solver's element-major (K, 4, Np)
+        q0_oracle = np.ascontiguousarray(np.swapaxes(q0, 0, 1)) if headline_is_c2 else None
+        out["cpu_baseline"] = cpu_baseline(workload, q0_oracle, gpu_stage_s)
     print(json.dumps(out), flush=True)
     torch.cuda.synchronize()
 

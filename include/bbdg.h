@@ -28,9 +28,12 @@
  *                Barycentric coordinate lambda_i belongs to local vertex i of the
  *                element; B_alpha = N!/alpha! lambda^alpha.
  *   Faces:       local face f is the face opposite local vertex f.
- *   Fields:      device arrays of shape (4, K, Np), row-major, in the order
- *                (p, u, v, w); element-major within a field.  Element type is
- *                double (BBDG_F64) or float (BBDG_F32) as chosen at create time.
+ *   Fields:      device arrays of shape (K, 4, Np), row-major: element-major,
+ *                each element's coefficients of p, u, v, w (in that order) in
+ *                one contiguous block of 4 Np values, so that an element's
+ *                state is read and written as one coalesced run.  Element type
+ *                is double (BBDG_F64) or float (BBDG_F32) as chosen at create
+ *                time.
  *   Geometry:    host array geo of shape (K, 10) double: d(lambda_i)/dx,
  *                d(lambda_i)/dy, d(lambda_i)/dz for i = 1, 2, 3 (9 values), then
  *                J = 3 V / 4 (V the element volume; J > 0 required).
@@ -163,7 +166,7 @@ int bbdg_basis(const bbdg_solver* s);
 int bbdg_info(const bbdg_solver* s, int* N, int* dtype, int64_t* K, int* Np);
 
 /* One right-hand-side evaluation: rhs = A(q) (mode BBDG_RHS_FULL), or only
- * its volume or surface part.  q and rhs are device (4, K, Np) arrays of the
+ * its volume or surface part.  q and rhs are device (K, 4, Np) arrays of the
  * solver's element type; they must not overlap. */
 int bbdg_rhs(bbdg_solver* s, const void* q, void* rhs, int mode, void* stream);
 
@@ -171,7 +174,7 @@ int bbdg_rhs(bbdg_solver* s, const void* q, void* rhs, int mode, void* stream);
  * second field buffer, 2 * 4 * K * Np elements. */
 size_t bbdg_work_bytes(const bbdg_solver* s);
 
-/* Advances q (device (4, K, Np), in/out) by `steps` LSRK4 steps of size dt
+/* Advances q (device (K, 4, Np), in/out) by `steps` LSRK4 steps of size dt
  * from time t0.  work: device, >= bbdg_work_bytes(s), 256-byte aligned; its
  * contents on entry are ignored.  steps >= 0, dt finite. */
 int bbdg_run(bbdg_solver* s, void* q, void* work, double t0, double dt, int64_t steps,
@@ -183,7 +186,7 @@ int bbdg_run(bbdg_solver* s, void* q, void* work, double t0, double dt, int64_t 
  * (64 MiB) that the library holds on every device it runs on until the
  * process ends, so that the call itself allocates nothing (no hipMalloc,
  * hipFree or allocating library routine).  Same arguments, kernels and
- * results as bbdg_run without `work`: q is the caller's device (4, K, Np)
+ * results as bbdg_run without `work`: q is the caller's device (K, 4, Np)
  * field, in/out.  Fails with BBDG_E_TOOBIG, before touching the device, when
  * bbdg_work_bytes(s) exceeds BBDG_NOALLOC_WORK_BYTES (e.g. FP64 with
  * 4 K Np > 1,048,576), and with BBDG_E_DEVICE if the array's address could
@@ -256,8 +259,8 @@ size_t bbdg_batched_work_bytes(const bbdg_solver* s, int64_t shots);
  * kernel launches of up to 1024 steps each (grid-wide barriers between the
  * stages), each preceded by a small kernel that tabulates the wavelet at its
  * stage times.
- *   q:        device (shots, 4, K, Np), in/out (shot-major; each shot is a
- *             (4, K, Np) field as above).
+ *   q:        device (shots, K, 4, Np), in/out (shot-major; each shot is a
+ *             (K, 4, Np) field as above).
  *   src_elem: device int32 (shots): source element of each shot, or -1 for a
  *             shot without source; NULL = no sources at all.
  *   src_coef: device (shots x Np) of the solver's element type: the
@@ -337,7 +340,7 @@ int bbdg_set_wavespeed(bbdg_solver* s, const double* c);
  * these sizes (0 for invalid sizes). */
 size_t bbdg_misfit_work_bytes(const bbdg_solver* s, int64_t shots, int R, int64_t steps, int64_t ckpt_every);
 
-/* Runs the batched forward problem from q0 (device (shots, 4, K, Np), or NULL
+/* Runs the batched forward problem from q0 (device (shots, K, 4, Np), or NULL
  * for zero initial states), keeps checkpoints and traces in work (device,
  * >= bbdg_misfit_work_bytes, 256-byte aligned) and writes J (device, one
  * double).  Arguments as bbdg_run_batched; obs: device (steps, shots, R) of

@@ -261,6 +261,7 @@ void bb_adjoint_kernel(AdjointArgs<T> A) {
 
     // ---- issue every load of this group together --------------------------------
     // own adjoint state and recorded pressure right-hand side
+    // (element-major fields: field f of node n of element e at e 4 Np + f Np + n)
     T qv[NPL][4], uv[NPL][4], pv[NPL];
     uint32_t noff[NPL];
 #pragma unroll
@@ -269,13 +270,13 @@ void bb_adjoint_kernel(AdjointArgs<T> A) {
       const int el = E == 1 ? 0 : v / Np;
       const int n = v - el * Np;
       const bool ok = (v < E * Np) && (e0 + el < K);
-      noff[r] = ok ? (uint32_t)((e0 + el) * Np + n) : 0u;
+      noff[r] = ok ? (uint32_t)((e0 + el) * 4 * Np + n) : 0u;
 #pragma unroll
       for (int f = 0; f < 4; ++f) {
-        qv[r][f] = ok ? A.qb[sb + f * KNp + noff[r]] : (T)0;
-        uv[r][f] = ok ? A.rb[sb + f * KNp + noff[r]] : (T)0;
+        qv[r][f] = ok ? A.qb[sb + f * Np + noff[r]] : (T)0;
+        uv[r][f] = ok ? A.rb[sb + f * Np + noff[r]] : (T)0;
       }
-      pv[r] = ok ? A.rec_p[shot * KNp + noff[r]] : (T)0;
+      pv[r] = ok ? A.rec_p[shot * KNp + (e0 + el) * Np + n] : (T)0;
     }
     // per face item: the neighbour's face adjoint (pull) and the recorded jumps
     T zq[NFI][2], rjv[NFI][2];
@@ -634,8 +635,8 @@ void bb_adjoint_kernel(AdjointArgs<T> A) {
       if (v >= E * Np || e0 + el >= K) continue;
 #pragma unroll
       for (int f = 0; f < 4; ++f) {
-        A.qb[sb + f * KNp + noff[r]] = qv[r][f] + dt * acc[r][f];
-        A.rb[sb + f * KNp + noff[r]] = a_s * uv[r][f];
+        A.qb[sb + f * Np + noff[r]] = qv[r][f] + dt * acc[r][f];
+        A.rb[sb + f * Np + noff[r]] = a_s * uv[r][f];
       }
     }
   }
@@ -694,12 +695,12 @@ __global__ void inject_receivers_kernel(int Np, int64_t K, int64_t shots, int R,
   if (t >= shots * Np) return;
   const int64_t s = t / Np;
   const int n = (int)(t - s * Np);
-  T* qp = qb + s * 4 * K * Np;  // pressure field of shot s
+  T* qs = qb + s * 4 * K * Np;  // fields of shot s (element-major)
   for (int r = 0; r < R; ++r) {
     const int32_t e = rec_elem[r];
     if (e < 0 || e >= K) continue;
     const T res = traces[s * R + r] - obs[s * R + r];
-    qp[(int64_t)e * Np + n] += res * rec_coef[(int64_t)r * Np + n];
+    qs[(int64_t)e * 4 * Np + n] += res * rec_coef[(int64_t)r * Np + n];  // pressure block of element e
   }
 }
 

@@ -23,7 +23,7 @@ struct StageArgs {
   int bc;
   int nt_store;  // 1: FP64 stage outputs with non-temporal stores (single-stage launches)
   // Batched multi-stage launches (mode kBatched): S shots stored shot-major
-  // (S, 4, K, Np); stage s reads buffer s % 2 of {qout, qalt} and writes the
+  // (S, K, 4, Np); stage s reads buffer s % 2 of {qout, qalt} and writes the
   // other; a Ricker point source per shot is added to the pressure equation;
   // receivers sample the pressure after every fifth stage.
   int64_t shots;
@@ -87,8 +87,8 @@ hipError_t launch_wavelet(double* amp, int64_t nstages, double t0, int64_t step0
 //   of this stage are added to gk (S, K) and gt (S, K, 4) in FP64.
 template <typename T>
 struct AdjointArgs {
-  T* rb;             // (S, 4, K, Np) in/out
-  T* qb;             // (S, 4, K, Np) in/out, own-element part
+  T* rb;             // (S, K, 4, Np) in/out
+  T* qb;             // (S, K, 4, Np) in/out, own-element part
   const T* z_in;     // (S, K, 4, 2, Nfp) of the previous reverse stage (pull != 0)
   T* z_out;          // (S, K, 4, 2, Nfp)
   const T* rec_p;    // (S, K, Np) record of this forward stage

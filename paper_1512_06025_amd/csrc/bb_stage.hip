@@ -167,7 +167,6 @@ struct Header {
 
 template <int N, typename T, int TW>
 __device__ __forceinline__ void load_header(Header<N, T, TW>& h, const StageArgs<T>& A, int64_t g, int tl) {
-  using S = Shape<N, T>;
   using M = Team<N, T, TW>;
   const int64_t e0 = g * M::E;
 #pragma unroll
@@ -439,7 +438,9 @@ void bb_stage_kernel(StageArgs<T> A) {
     const int64_t shot = kBatch ? (int64_t)__builtin_amdgcn_readfirstlane((uint32_t)g / (uint32_t)G) : 0;
     const int64_t e0 = (g - shot * G) * E;
     const int64_t sb = shot * 4 * KNp;  // this shot's fields
-    const T* qin_f[4] = {qin_b + sb, qin_b + sb + KNp, qin_b + sb + 2 * KNp, qin_b + sb + 3 * KNp};
+    // element-major fields: element e holds p, u, v, w of its Np nodes in
+    // one contiguous block of 4 Np values; qin_f[f] + e 4 Np + n is field f
+    const T* qin_f[4] = {qin_b + sb, qin_b + sb + Np, qin_b + sb + 2 * Np, qin_b + sb + 3 * Np};
     T* const res_s = A.res + (kUpdate ? sb : 0);
     T* const qout_s = qout_b + sb;
     // Lane-derived addresses are cheap to recompute; hiding the lane id from
@@ -467,19 +468,19 @@ void bb_stage_kernel(StageArgs<T> A) {
 
     // ---- issue this group's loads: own q, residual, neighbour traces --------
     T qv[NPL][4], rv[NPL][4];
-    uint32_t noff[NPL];
+    uint32_t noff[NPL];  // e 4 Np + n of the thread's nodes (field p)
 #pragma unroll
     for (int r = 0; r < NPL; ++r) {
       const int v = lane + TPE * r;
       const int el = E == 1 ? 0 : v / Np;
       const int n = v - el * Np;
       const bool ok = (v < E * Np) && (e0 + el < K);
-      noff[r] = ok ? (uint32_t)((e0 + el) * Np + n) : 0u;
+      noff[r] = ok ? (uint32_t)((e0 + el) * 4 * Np + n) : 0u;
 #pragma unroll
       for (int f = 0; f < 4; ++f) qv[r][f] = ld(qin_f[f], noff[r]);
       if (kUpdate && read_res && !S::LATE_RES) {
 #pragma unroll
-        for (int f = 0; f < 4; ++f) rv[r][f] = ldn<NT>(res_s + f * KNp, noff[r]);
+        for (int f = 0; f < 4; ++f) rv[r][f] = ldn<NT>(res_s + f * Np, noff[r]);
       } else {
 #pragma unroll
         for (int f = 0; f < 4; ++f) rv[r][f] = 0;
@@ -497,7 +498,7 @@ void bb_stage_kernel(StageArgs<T> A) {
         if (el < (unsigned)E && gg < (unsigned)Nfp && e0 + el < K) {
           const int nb = she[w][el * 4 + f];
           const int info = shf[w][el * 4 + f];
-          if (nb >= 0) off = (uint32_t)nb * Np + t_nbr[((info & 3) * 6 + (info >> 2)) * Nfp + gg];
+          if (nb >= 0) off = (uint32_t)nb * (4 * Np) + t_nbr[((info & 3) * 6 + (info >> 2)) * Nfp + gg];
         }
 #pragma unroll
         for (int fl = 0; fl < 4; ++fl) tr[r][fl] = ld(qin_f[fl], off);
@@ -609,7 +610,7 @@ void bb_stage_kernel(StageArgs<T> A) {
 #pragma unroll
         for (int r = 0; r < NPL; ++r) {
 #pragma unroll
-          for (int f = 0; f < 4; ++f) rv[r][f] = ldn<NT>(res_s + f * KNp, noff[r]);
+          for (int f = 0; f < 4; ++f) rv[r][f] = ldn<NT>(res_s + f * Np, noff[r]);
         }
       }
     }
@@ -747,17 +748,17 @@ void bb_stage_kernel(StageArgs<T> A) {
       if (v >= E * Np || e0 + el >= K) continue;
       const uint32_t off = noff[r];
       if constexpr (kUpdate) {
-        if constexpr (kRecord) A.rec_p[(stage * A.shots + shot) * KNp + off] = rhs[r][0];
+        if constexpr (kRecord) A.rec_p[(stage * A.shots + shot) * KNp + (e0 + el) * Np + (v - el * Np)] = rhs[r][0];
         const T dt = kBatch ? (T)A.dtd : A.dt;
 #pragma unroll
         for (int f = 0; f < 4; ++f) {
           const T rs = dt * rhs[r][f] + rk_a * rv[r][f];
-          st<NT>(res_s + f * KNp, off, rs);
-          st<NT>(qout_s + f * KNp, off, qv[r][f] + rk_b * rs);
+          st<NT>(res_s + f * Np, off, rs);
+          st<NT>(qout_s + f * Np, off, qv[r][f] + rk_b * rs);
         }
       } else {
 #pragma unroll
-        for (int f = 0; f < 4; ++f) st<NT>(qout_s + f * KNp, off, rhs[r][f]);
+        for (int f = 0; f < 4; ++f) st<NT>(qout_s + f * Np, off, rhs[r][f]);
       }
     }
   }  // element groups
@@ -775,7 +776,7 @@ void bb_stage_kernel(StageArgs<T> A) {
         const int32_t re = A.rec_elem[rr];
         T acc = (T)NAN;
         if (re >= 0 && re < K) {
-          const T* pr = qout_b + sh * 4 * KNp + (int64_t)re * Np;
+          const T* pr = qout_b + sh * 4 * KNp + (int64_t)re * 4 * Np;  // p block of element re
           const T* cr = A.rec_coef + (int64_t)rr * Np;
           acc = 0;
 #pragma unroll 8

@@ -68,7 +68,6 @@ __global__ __launch_bounds__(256) void ept_flux_kernel(NodalArgs<T> A, T* __rest
   __syncthreads();
   const int64_t K = A.K;
   const int64_t items = K * NL;
-  const uint32_t KNp = (uint32_t)(K * Np);
   const size_t KL = (size_t)K * NL;
   for (int64_t it = (int64_t)blockIdx.x * 256 + threadIdx.x; it < items; it += (int64_t)gridDim.x * 256) {
     const int64_t e = it / NL;
@@ -86,16 +85,16 @@ __global__ __launch_bounds__(256) void ept_flux_kernel(NodalArgs<T> A, T* __rest
       lz = ge[3 * (f - 1) + 2];
     }
     const T gx = (T)(-2.0 * lx), gy = (T)(-2.0 * ly), gz = (T)(-2.0 * lz);
-    const uint32_t own = (uint32_t)e * Np + t_fnode[m];
-    const T pm = A.qin[own], um = A.qin[KNp + own], vm = A.qin[2 * KNp + own], wm = A.qin[3 * KNp + own];
+    const uint32_t own = (uint32_t)e * (4 * Np) + t_fnode[m];  // element-major fields
+    const T pm = A.qin[own], um = A.qin[Np + own], vm = A.qin[2 * Np + own], wm = A.qin[3 * Np + own];
     const T gum = gx * um + gy * vm + gz * wm;
     const int32_t nb = A.etoe[e * 4 + f];
     T jp, jgu;
     if (nb >= 0) {
       const uint32_t info = A.etofo[e * 4 + f];
-      const uint32_t o = (uint32_t)nb * Np + t_nbr[((info & 3) * 6 + (info >> 2)) * Nfp + g];
+      const uint32_t o = (uint32_t)nb * (4 * Np) + t_nbr[((info & 3) * 6 + (info >> 2)) * Nfp + g];
       jp = A.qin[o] - pm;
-      jgu = gx * A.qin[KNp + o] + gy * A.qin[2 * KNp + o] + gz * A.qin[3 * KNp + o] - gum;
+      jgu = gx * A.qin[Np + o] + gy * A.qin[2 * Np + o] + gz * A.qin[3 * Np + o] - gum;
     } else if (A.bc == 0) {  // rigid wall mirror
       jp = 0;
       jgu = (T)(-2) * gum;
@@ -123,11 +122,11 @@ struct EptStage {
 };
 
 // Stages values [n0, n0 + J) of the 4 arrays src + c * cstride (element k's
-// values at k * len) for the wave's elements e0 .. e0 + 63 into
+// len values at k * estride) for the wave's elements e0 .. e0 + 63 into
 // s[c][jj][lane]; out-of-range entries read as zero.
 template <typename T>
-__device__ __forceinline__ void ept_stage(T* s, const T* src, size_t cstride, int len, int n0, int64_t e0, int64_t K,
-                                          int lane) {
+__device__ __forceinline__ void ept_stage(T* s, const T* src, size_t cstride, size_t estride, int len, int n0,
+                                          int64_t e0, int64_t K, int lane) {
   constexpr int J = EptStage<T>::J, ROW = EptStage<T>::ROW;
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
@@ -137,7 +136,7 @@ __device__ __forceinline__ void ept_stage(T* s, const T* src, size_t cstride, in
       const int el = idx / J, jj = idx % J;
       const int n = n0 + jj;
       T v = 0;
-      if (n < len && e0 + el < K) v = src[c * cstride + (size_t)(e0 + el) * len + n];
+      if (n < len && e0 + el < K) v = src[c * cstride + (size_t)(e0 + el) * estride + n];
       s[(c * J + jj) * ROW + el] = v;
     }
   }
@@ -175,7 +174,6 @@ __global__ __launch_bounds__(256) void nodal_ept_kernel(NodalArgs<T> A, const T*
   T* s = stage_buf[w];
   const int64_t e = e0 + lane;
   const bool live = e < K;
-  const uint32_t KNp = (uint32_t)(K * Np);
 
   // per-element geometry (see kGeoStride)
   T gl[9];
@@ -198,7 +196,7 @@ __global__ __launch_bounds__(256) void nodal_ept_kernel(NodalArgs<T> A, const T*
       for (int j0 = 0; j0 < Np; j0 += J) {
         const int jn = Np - j0 < J ? Np - j0 : J;
         __syncthreads();  // the previous chunk's tile and buffers are consumed
-        ept_stage<T>(s, A.qin, KNp, Np, j0, e0, K, lane);
+        ept_stage<T>(s, A.qin, Np, 4 * Np, Np, j0, e0, K, lane);  // element-major fields
         for (int t = tid; t < jn * B * 4; t += 256) {
           const int jj = t / (B * 4), rest = t - jj * (B * 4);
           op_tile[t] = opv[((size_t)(j0 + jj) * NpB + i0) * 4 + rest];
@@ -236,7 +234,7 @@ __global__ __launch_bounds__(256) void nodal_ept_kernel(NodalArgs<T> A, const T*
       for (int m0 = 0; m0 < NL; m0 += J) {
         const int mn = NL - m0 < J ? NL - m0 : J;
         __syncthreads();
-        ept_stage<T>(s, F, (size_t)K * NL, NL, m0, e0, K, lane);
+        ept_stage<T>(s, F, (size_t)K * NL, NL, NL, m0, e0, K, lane);
         for (int t = tid; t < mn * B; t += 256) {
           const int jj = t / B, b = t - jj * B;
           op_tile[t] = opl[(size_t)(m0 + jj) * NpB + i0 + b];
@@ -272,7 +270,7 @@ __global__ __launch_bounds__(256) void nodal_ept_kernel(NodalArgs<T> A, const T*
       for (int idx = lane; idx < 64 * B; idx += 64) {
         const int el = idx / B, b = idx % B;
         if (b >= bn || e0 + el >= K) continue;
-        const uint32_t o = fl * KNp + (uint32_t)(e0 + el) * Np + i0 + b;
+        const uint32_t o = (uint32_t)(e0 + el) * (4 * Np) + fl * Np + i0 + b;
         const T rhs = s[el * (B + 1) + b];
         if constexpr (MODE == kStage) {
           const T rs = A.dt * rhs + (A.read_res ? A.rk_a * A.res[o] : (T)0);

@@ -140,7 +140,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void n
   if (lb >= blocks) return;  // the whole workgroup
   const int tid = threadIdx.x;
   const int64_t K = A.K;
-  const uint32_t KNp = (uint32_t)(K * Np);
   const int64_t e0 = lb * EB;
 
   for (int i = tid; i < 24 * Nfp; i += 256) t_nbr[i] = A.tab[L.nbrnode + i];
@@ -159,7 +158,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void n
     const int k = idx / NC, col = idx - k * NC;
     const int el = col >> 2, fl = col & 3;
     T v = 0;
-    if (k < Np && e0 + el < K) v = A.qin[fl * KNp + (uint32_t)(e0 + el) * Np + k];
+    if (k < Np && e0 + el < K) v = A.qin[(uint32_t)(e0 + el) * (4 * Np) + fl * Np + k];
     buf[k * NCP + col] = v;
   }
   __syncthreads();
@@ -247,9 +246,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void n
       T jp, jgu;
       if (nb >= 0) {
         const int info = shf[el * 4 + f];
-        const uint32_t o = (uint32_t)nb * Np + t_nbr[((info & 3) * 6 + (info >> 2)) * Nfp + g];
+        const uint32_t o = (uint32_t)nb * (4 * Np) + t_nbr[((info & 3) * 6 + (info >> 2)) * Nfp + g];
         jp = A.qin[o] - pm;
-        jgu = gx * A.qin[KNp + o] + gy * A.qin[2 * KNp + o] + gz * A.qin[3 * KNp + o] - gum;
+        jgu = gx * A.qin[Np + o] + gy * A.qin[2 * Np + o] + gz * A.qin[3 * Np + o] - gum;
       } else if (A.bc == 0) {  // rigid wall mirror
         jp = 0;
         jgu = (T)(-2) * gum;
@@ -307,7 +306,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void n
       for (int rr = 0; rr < 4; ++rr) {
         const int row = rt * 16 + M::row(kq, rr);
         if (row >= Np) continue;
-        const uint32_t o = fl * KNp + (uint32_t)e * Np + row;
+        const uint32_t o = (uint32_t)e * (4 * Np) + fl * Np + row;
         if constexpr (MODE == kStage) {
           const T rs = A.dt * rhs[r][ct][rr] + (A.read_res ? A.rk_a * A.res[o] : (T)0);
           A.res[o] = rs;

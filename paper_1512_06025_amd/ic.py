@@ -41,9 +41,10 @@ def interpolate(N, VX, EToV, func):
 
 
 def initial_state(N, VX, EToV, p0, basis="bb"):
-    """(4, K, Np) float64 state with p interpolated from p0 and zero velocity:
-    Bernstein coefficients (basis="bb") or lattice values (basis="nodal")."""
+    """(K, 4, Np) float64 state, the solver's element-major field layout, with
+    p interpolated from p0 and zero velocity: Bernstein coefficients
+    (basis="bb") or lattice values (basis="nodal")."""
     K = np.asarray(EToV).shape[0]
-    q = np.zeros((4, K, alpha_table(N).shape[0]))
-    q[0] = interpolate(N, VX, EToV, p0) if basis == "bb" else lattice_values(N, VX, EToV, p0)
+    q = np.zeros((K, 4, alpha_table(N).shape[0]))
+    q[:, 0] = interpolate(N, VX, EToV, p0) if basis == "bb" else lattice_values(N, VX, EToV, p0)
     return q

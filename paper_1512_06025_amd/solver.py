@@ -89,7 +89,8 @@ class Solver:
     basis="bb" is the Bernstein-Bezier solver; basis="nodal" the dense nodal
     comparator applied by MFMA, basis="nodal_ept" the element-per-thread one
     (fields are then nodal values at the lattice points).
-    Field tensors are torch CUDA tensors of shape (4, K, Np) with dtype
+    Field tensors are torch CUDA tensors of shape (K, 4, Np) (element-major:
+    element k's p, u, v, w coefficients are q[k, 0..3, :]) with dtype
     float64 (dtype="f64") or float32 (dtype="f32")."""
 
     def __init__(self, N, mesh, c, dtype="f64", bc="rigid", device=0, basis="bb"):
@@ -117,13 +118,13 @@ class Solver:
     def _check_field(self, t):
         import torch
         if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == self.torch_dtype
-                and tuple(t.shape) == (4, self.K, self.Np) and t.is_contiguous()):
-            raise ValueError("expected a contiguous CUDA tensor (4, %d, %d) of %s"
+                and tuple(t.shape) == (self.K, 4, self.Np) and t.is_contiguous()):
+            raise ValueError("expected a contiguous CUDA tensor (%d, 4, %d) of %s"
                              % (self.K, self.Np, self.torch_dtype))
 
     def empty_field(self):
         import torch
-        return torch.empty((4, self.K, self.Np), dtype=self.torch_dtype, device=self.device)
+        return torch.empty((self.K, 4, self.Np), dtype=self.torch_dtype, device=self.device)
 
     def rhs(self, q, mode=_lib.BBDG_RHS_FULL, out=None, stream=None):
         self._check_field(q)
@@ -179,7 +180,7 @@ class BatchedSolver:
 
     sources: (S, 3) source positions (one Ricker point source per shot) or
     None; receivers: (R, 3) positions shared by all shots.  States are CUDA
-    tensors (S, 4, K, Np); run() returns the receiver traces (steps, S, R).
+    tensors (S, K, 4, Np); run() returns the receiver traces (steps, S, R).
     wpb = 0 lets bbdg_tune_batched pick the waves per workgroup on first use."""
 
     def __init__(self, N, mesh, c, shots, sources=None, receivers=None, f0=8.0, ts=0.125,
@@ -224,7 +225,7 @@ class BatchedSolver:
     def empty_state(self):
         import torch
         s = self.solver
-        return torch.zeros((self.S, 4, s.K, s.Np), dtype=s.torch_dtype, device=s.device)
+        return torch.zeros((self.S, s.K, 4, s.Np), dtype=s.torch_dtype, device=s.device)
 
     def _buffer(self, nbytes):
         import torch
@@ -252,8 +253,8 @@ class BatchedSolver:
         import torch
         s = self.solver
         if not (isinstance(q, torch.Tensor) and q.is_cuda and q.dtype == s.torch_dtype and q.is_contiguous()
-                and tuple(q.shape) == (self.S, 4, s.K, s.Np)):
-            raise ValueError("expected a contiguous CUDA tensor (%d, 4, %d, %d) of %s"
+                and tuple(q.shape) == (self.S, s.K, 4, s.Np)):
+            raise ValueError("expected a contiguous CUDA tensor (%d, %d, 4, %d) of %s"
                              % (self.S, s.K, s.Np, s.torch_dtype))
         if self.wpb == 0:
             self.tune(stream)

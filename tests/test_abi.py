@@ -215,3 +215,23 @@ def test_bernstein_eval_matches_oracle(N):
     np.testing.assert_allclose(P.bernstein_eval(N, lam), dg.bernstein_eval(N, lam), rtol=1e-13, atol=1e-15)
     # partition of unity
     np.testing.assert_allclose(P.bernstein_eval(N, lam).sum(axis=1), 1.0, rtol=1e-14)
+
+
+def test_initial_state_is_element_major():
+    """The package's initial-state helper returns the solver's element-major
+    field layout (K, 4, Np): element k's pressure coefficients at [k, 0].  For
+    a polynomial of degree <= N its interpolation equals the oracle's L2
+    projection (both reproduce the polynomial exactly)."""
+    from oracle import dg
+    from paper_1512_06025_amd import ic
+    VX, EToV = workload.kuhn_cube_mesh(2, 0.1, drop_last=3)
+    N = 3
+    prob = dg.Problem(VX, EToV, N, np.ones(EToV.shape[0]))
+
+    def p0(x, y, z):
+        return 1.0 + 2.0 * x - y + 3.0 * z * x - 0.5 * y * y * z
+
+    got = ic.initial_state(N, VX, EToV, p0)
+    assert got.shape == (prob.K, 4, prob.Np)
+    want = dg.initial_state(prob, p0)
+    np.testing.assert_allclose(np.swapaxes(got, 0, 1), want, rtol=0, atol=1e-11)

@@ -27,6 +27,16 @@ def _host(x):
     return x.detach().to("cpu", torch.float64).numpy()
 
 
+def _host_state(q):
+    """Device shots (S, K, 4, Np) -> oracle layout (S, 4, K, Np), float64."""
+    return np.swapaxes(_host(q), 1, 2)
+
+
+def _dev_state(q0, dtype):
+    """Oracle shots (S, 4, K, Np) -> the library's element-major (S, K, 4, Np)."""
+    return torch.from_numpy(np.ascontiguousarray(np.swapaxes(q0, 1, 2))).to("cuda", dtype)
+
+
 def _case(N, n=2, drop_last=5, shots=4, nrec=5, seed=3):
     import paper_1512_06025_amd as P
     VX, EToV = workload.kuhn_cube_mesh(n, 0.1, drop_last=drop_last)
@@ -55,7 +65,7 @@ def test_batched_parity(N, dtype, wpb, steps=7):
     q0[S - 1] = workload.random_coeffs(prob.K, prob.Np, seed=77)
     if dtype == "f32":
         q0 = q0.astype(np.float32).astype(np.float64)
-    q = torch.from_numpy(q0).to("cuda", bs.solver.torch_dtype)
+    q = _dev_state(q0, bs.solver.torch_dtype)
     tr = bs.run(q, dt, steps, t0=t0)
 
     se, sl = prob.locate(src)
@@ -64,9 +74,9 @@ def test_batched_parity(N, dtype, wpb, steps=7):
     np.testing.assert_array_equal(_host(bs.rec_elem), re)
     se[-1] = -1
     want_q, want_tr, scale = prob.run_shots(q0, dt, steps, se, sl, F0, TS, re, rl, t0=t0, trace_scales=True)
-    assert _rel(_host(q), want_q) < TOL[dtype]
+    assert _rel(_host_state(q), want_q) < TOL[dtype]
     for s in range(S):
-        assert _rel(_host(q)[s], want_q[s]) < TOL[dtype], s
+        assert _rel(_host_state(q)[s], want_q[s]) < TOL[dtype], s
     assert tr.shape == (steps, S, len(rec))
     # a trace is a linear functional sum_n W_rn p_n whose terms cancel (by a
     # factor of several hundred at N = 9 on this rough initial state), so the
@@ -129,7 +139,7 @@ def test_barrier_timeout_drains_and_reports():
     se, sl = prob.locate(src)
     re, rl = prob.locate(rec)
     want_q, want_tr = prob.run_shots(np.zeros((S, 4, prob.K, prob.Np)), dt, steps, se, sl, F0, TS, re, rl, t0=0.1)
-    assert _rel(_host(q), want_q) < TOL["f64"]
+    assert _rel(_host_state(q), want_q) < TOL["f64"]
     bs.close()
 
 
@@ -202,7 +212,7 @@ def test_c4_full_size_sampled():
     q = bs.empty_state()
     tr = bs.run(q, dt, steps, t0=t0)
     bs.check()
-    qh = _host(q)
+    qh = _host_state(q)
     prob = dg.Problem(VX, EToV, cfg["N"], c)
     se, sl = prob.locate(src)
     re, rl = prob.locate(rec)

@@ -38,6 +38,16 @@ def _host(x):
     return x.detach().to("cpu", torch.float64).numpy()
 
 
+def _dev(q0, dtype):
+    """Oracle state (4, K, Np) -> the library's element-major (K, 4, Np)."""
+    return torch.from_numpy(np.ascontiguousarray(np.swapaxes(q0, 0, 1))).to("cuda", dtype)
+
+
+def _host_field(q):
+    """Device field (K, 4, Np) -> oracle layout (4, K, Np), float64."""
+    return np.swapaxes(_host(q), 0, 1)
+
+
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_c2_one_step(dtype):
     import paper_1512_06025_amd as P
@@ -47,10 +57,10 @@ def test_c2_one_step(dtype):
     if dtype == "f32":
         q0 = q0.astype(np.float32).astype(np.float64)
     s = P.Solver(cfg["N"], P.mesh_geometry(VX, EToV), c, dtype=dtype)
-    q = torch.from_numpy(q0).to("cuda", s.torch_dtype)
+    q = _dev(q0, s.torch_dtype)
     s.run(q, cfg["dt"], 1)
     want = prob.lsrk4(q0, cfg["dt"], 1)
-    assert _rel(_host(q), want) < TOL[dtype]
+    assert _rel(_host_field(q), want) < TOL[dtype]
     s.close()
 
 
@@ -68,10 +78,10 @@ def test_c2_mesh_high_order_one_step_nontemporal_stores(N):
     q0 = workload.random_coeffs(prob.K, prob.Np, seed=22)
     s = P.Solver(N, P.mesh_geometry(VX, EToV), c, dtype="f64")
     assert s.nontemporal_stores()
-    q = torch.from_numpy(q0).to("cuda", s.torch_dtype)
+    q = _dev(q0, s.torch_dtype)
     s.run(q, cfg["dt"], 1)
     want = prob.lsrk4(q0, cfg["dt"], 1)
-    assert _rel(_host(q), want) < TOL["f64"]
+    assert _rel(_host_field(q), want) < TOL["f64"]
     s.close()
 
 
@@ -115,7 +125,7 @@ def test_c3_rhs_sampled(N, dtype):
     if dtype == "f32":
         q = q.astype(np.float32).astype(np.float64)
     s = P.Solver(N, mesh, c, dtype=dtype)
-    got = _host(s.rhs(torch.from_numpy(q).to("cuda", s.torch_dtype)))
+    got = _host_field(s.rhs(_dev(q, s.torch_dtype)))
     s.close()
     rng = np.random.default_rng(400 + N)
     # include elements on the domain boundary and the last element

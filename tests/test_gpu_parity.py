@@ -29,12 +29,16 @@ def _setup(n, N, jitter=0.1, c=(1.0, 3.0), bc="rigid", drop_last=0):
 
 
 def _to_dev(x, dtype):
-    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda", torch.float64 if dtype == "f64" else torch.float32)
+    """Oracle state (4, K, Np) -> device field in the library's element-major
+    layout (K, 4, Np)."""
+    return torch.from_numpy(np.ascontiguousarray(np.swapaxes(x, 0, 1))).to(
+        "cuda", torch.float64 if dtype == "f64" else torch.float32)
 
 
 def _host(x):
+    """Device field (K, 4, Np) -> oracle layout (4, K, Np), float64."""
     torch.cuda.synchronize()
-    return x.detach().to("cpu", torch.float64).numpy()
+    return np.swapaxes(x.detach().to("cpu", torch.float64).numpy(), 0, 1)
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])

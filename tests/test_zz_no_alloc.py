@@ -58,7 +58,8 @@ def test_noalloc_matches_run_twice(dtype):
             if dtype == "f32":
                 q0 = q0.astype(np.float32).astype(np.float64)
             dt = 0.5 / (n * 3.0 * (N + 1) ** 2)
-            qa = torch.from_numpy(q0).to("cuda", tdt)
+            # the library's element-major field layout (K, 4, Np)
+            qa = torch.from_numpy(np.ascontiguousarray(np.swapaxes(q0, 0, 1))).to("cuda", tdt)
             qb = qa.clone()
             work = torch.empty(wb // qa.element_size(), dtype=tdt, device="cuda")
             _lib.check(lib.bbdg_run(h, qa.data_ptr(), work.data_ptr(), 0.0, dt, steps, sp), "bbdg_run")
@@ -67,7 +68,7 @@ def test_noalloc_matches_run_twice(dtype):
             assert torch.equal(qa, qb), (n, N, dtype)
             prob = dg.Problem(VX, EToV, N, c)
             want = prob.lsrk4(q0, dt, steps)
-            got = qb.to("cpu", torch.float64).numpy()
+            got = np.swapaxes(qb.to("cpu", torch.float64).numpy(), 0, 1)
             err = float(np.linalg.norm(got - want) / np.linalg.norm(want))
             assert err < TOL[dtype], (n, N, dtype, err)
             del work
