@@ -186,17 +186,11 @@ __device__ __forceinline__ void load_header(Header<N, T, TW>& h, const StageArgs
   }
 }
 
-// Element-offset access with a 32-bit byte offset (4 K Np < 2^31 is enforced
-// at create time), so loads and stores use a scalar base plus a 32-bit
-// vector offset.
-template <typename T>
-__device__ __forceinline__ T ld(const T* base, uint32_t idx) {
-  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + (idx * (uint32_t)sizeof(T)));
-}
 // Residual loads (read once, by the element itself): non-temporal with NT.
+// Element offsets are 32-bit (4 K Np < 2^31 is enforced at create time); the
+// byte address is formed in 64 bits, so fields larger than 4 GiB are fine.
 template <bool NT, typename T>
-__device__ __forceinline__ T ldn(const T* base, uint32_t idx) {
-  const T* p = reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + (idx * (uint32_t)sizeof(T)));
+__device__ __forceinline__ T ldn(const T* p) {
   if constexpr (NT) return __builtin_nontemporal_load(p); else return *p;
 }
 
@@ -205,8 +199,7 @@ __device__ __forceinline__ T ldn(const T* base, uint32_t idx) {
 // run-time branch between the two stores is merged by the compiler into one
 // plain store.)
 template <bool NT, typename T>
-__device__ __forceinline__ void st(T* base, uint32_t idx, T x) {
-  T* p = reinterpret_cast<T*>(reinterpret_cast<char*>(base) + (idx * (uint32_t)sizeof(T)));
+__device__ __forceinline__ void st(T* p, T x) {
   if constexpr (NT) {
     __builtin_nontemporal_store(x, p);
   } else {
@@ -439,8 +432,9 @@ void bb_stage_kernel(StageArgs<T> A) {
     const int64_t e0 = (g - shot * G) * E;
     const int64_t sb = shot * 4 * KNp;  // this shot's fields
     // element-major fields: element e holds p, u, v, w of its Np nodes in
-    // one contiguous block of 4 Np values; qin_f[f] + e 4 Np + n is field f
-    const T* qin_f[4] = {qin_b + sb, qin_b + sb + Np, qin_b + sb + 2 * Np, qin_b + sb + 3 * Np};
+    // one contiguous block of 4 Np values; field f of node n is at
+    // e 4 Np + f Np + n, so one address per node serves all four fields
+    const T* const qin_s = qin_b + sb;
     T* const res_s = A.res + (kUpdate ? sb : 0);
     T* const qout_s = qout_b + sb;
     // Lane-derived addresses are cheap to recompute; hiding the lane id from
@@ -476,11 +470,13 @@ void bb_stage_kernel(StageArgs<T> A) {
       const int n = v - el * Np;
       const bool ok = (v < E * Np) && (e0 + el < K);
       noff[r] = ok ? (uint32_t)((e0 + el) * 4 * Np + n) : 0u;
+      const T* qp = qin_s + noff[r];
 #pragma unroll
-      for (int f = 0; f < 4; ++f) qv[r][f] = ld(qin_f[f], noff[r]);
+      for (int f = 0; f < 4; ++f) qv[r][f] = qp[f * Np];
       if (kUpdate && read_res && !S::LATE_RES) {
+        const T* rp = res_s + noff[r];
 #pragma unroll
-        for (int f = 0; f < 4; ++f) rv[r][f] = ldn<NT>(res_s + f * Np, noff[r]);
+        for (int f = 0; f < 4; ++f) rv[r][f] = ldn<NT>(rp + f * Np);
       } else {
 #pragma unroll
         for (int f = 0; f < 4; ++f) rv[r][f] = 0;
@@ -500,8 +496,9 @@ void bb_stage_kernel(StageArgs<T> A) {
           const int info = shf[w][el * 4 + f];
           if (nb >= 0) off = (uint32_t)nb * (4 * Np) + t_nbr[((info & 3) * 6 + (info >> 2)) * Nfp + gg];
         }
+        const T* tp = qin_s + off;
 #pragma unroll
-        for (int fl = 0; fl < 4; ++fl) tr[r][fl] = ld(qin_f[fl], off);
+        for (int fl = 0; fl < 4; ++fl) tr[r][fl] = tp[fl * Np];
       }
     }
     // ---- prefetch the next group's header -----------------------------------
@@ -609,8 +606,9 @@ void bb_stage_kernel(StageArgs<T> A) {
       if (read_res) {
 #pragma unroll
         for (int r = 0; r < NPL; ++r) {
+          const T* rp = res_s + noff[r];
 #pragma unroll
-          for (int f = 0; f < 4; ++f) rv[r][f] = ldn<NT>(res_s + f * Np, noff[r]);
+          for (int f = 0; f < 4; ++f) rv[r][f] = ldn<NT>(rp + f * Np);
         }
       }
     }
@@ -746,19 +744,20 @@ void bb_stage_kernel(StageArgs<T> A) {
       const int v = lane + TPE * r;
       const int el = E == 1 ? 0 : v / Np;
       if (v >= E * Np || e0 + el >= K) continue;
-      const uint32_t off = noff[r];
+      T* const rp = res_s + noff[r];
+      T* const op = qout_s + noff[r];
       if constexpr (kUpdate) {
         if constexpr (kRecord) A.rec_p[(stage * A.shots + shot) * KNp + (e0 + el) * Np + (v - el * Np)] = rhs[r][0];
         const T dt = kBatch ? (T)A.dtd : A.dt;
 #pragma unroll
         for (int f = 0; f < 4; ++f) {
           const T rs = dt * rhs[r][f] + rk_a * rv[r][f];
-          st<NT>(res_s + f * Np, off, rs);
-          st<NT>(qout_s + f * Np, off, qv[r][f] + rk_b * rs);
+          st<NT>(rp + f * Np, rs);
+          st<NT>(op + f * Np, qv[r][f] + rk_b * rs);
         }
       } else {
 #pragma unroll
-        for (int f = 0; f < 4; ++f) st<NT>(qout_s + f * Np, off, rhs[r][f]);
+        for (int f = 0; f < 4; ++f) st<NT>(op + f * Np, rhs[r][f]);
       }
     }
   }  // element groups
