@@ -73,9 +73,13 @@ struct Shape {
   // one wave fills 84 of 128)
   static constexpr int TW = (N == 4 || N == 6) ? 4 : (sizeof(T) == 8 ? (N >= 9 ? 4 : (N == 8 ? 3 : 1)) : 1);
   // faces per lift batch (bounds the LDS of the face vectors), for one-wave
-  // teams and for workgroup teams
+  // teams and for workgroup teams (measured, 196,608 tets: all four faces in
+  // one batch of a workgroup team instead of two batches of two save a
+  // round of flux, L_0 and reduction barriers, 8 % at N = 8 and 4 % at N = 4
+  // in FP64, although at N = 6 and 9 the larger LDS costs one workgroup per
+  // CU and the two balance)
   static constexpr int FB1 = sizeof(T) == 8 ? (N >= 8 ? 1 : (N >= 6 ? 2 : 4)) : (N >= 8 ? 2 : 4);
-  static constexpr int FBT = 2;
+  static constexpr int FBT = 4;
   // per-element derived geometry (type T): grad lambda_0..3 (12), kappa, pad,
   // then per face f at 16 + 6 f: g_x, g_y, g_z, a_p, a_u, b_u with
   //   sp = a_p [[p]] - a_u g.[[u]],  su = b_u g.[[u]] - [[p]]/2.
