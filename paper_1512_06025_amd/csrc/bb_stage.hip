@@ -45,6 +45,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "bb_common.hpp"
 #include "bb_launch.hpp"
@@ -107,11 +108,9 @@ struct Team {
   using S = Shape<N, T>;
   static constexpr int TPE = 64 * TW;
   static constexpr int E = TPE / S::Np > 1 ? TPE / S::Np : 1;    // elements per group
-  static constexpr int HG = E * kGeoStride;                       // header doubles per group
   static constexpr int NPL = (E * S::Np + TPE - 1) / TPE;         // nodes per thread
   static constexpr int SF = item_stride(S::Nfp, E * 4, TPE);      // face-item position stride
   static constexpr int NFI = (E * 4 * SF + TPE - 1) / TPE;        // face items per thread
-  static constexpr int NHG = (HG + TPE - 1) / TPE;
   static constexpr int NHE = (E * 4 + TPE - 1) / TPE;
 };
 
@@ -162,9 +161,15 @@ struct Ell {
   static constexpr double value(int j) { return ((j & 1) ? -1.0 : 1.0) * binom(N, j) / (1.0 + j); }
 };
 
+// Header of an element group in registers (prefetched one group ahead): the
+// double geometry (FP64, derived per element in the kernel) or the derived
+// geometry in float (FP32, computed once on the host), and the connectivity.
 template <int N, typename T, int TW>
 struct Header {
-  double geo[Team<N, T, TW>::NHG];
+  static constexpr bool kTG = sizeof(T) == 4;
+  static constexpr int GS = kTG ? kTGeoStride : kGeoStride;  // header words per element
+  static constexpr int NG = (Team<N, T, TW>::E * GS + Team<N, T, TW>::TPE - 1) / Team<N, T, TW>::TPE;
+  typename std::conditional<kTG, T, double>::type geo[NG];
   int32_t etoe[Team<N, T, TW>::NHE];
   uint32_t fo[Team<N, T, TW>::NHE];
 };
@@ -172,13 +177,18 @@ struct Header {
 template <int N, typename T, int TW>
 __device__ __forceinline__ void load_header(Header<N, T, TW>& h, const StageArgs<T>& A, int64_t g, int tl) {
   using M = Team<N, T, TW>;
+  using H = Header<N, T, TW>;
   const int64_t e0 = g * M::E;
 #pragma unroll
-  for (int r = 0; r < M::NHG; ++r) {
+  for (int r = 0; r < H::NG; ++r) {
     const int v = tl + M::TPE * r;
-    int64_t idx = e0 * kGeoStride + v;
-    if (v >= M::HG || idx >= A.K * kGeoStride) idx = 0;
-    h.geo[r] = A.geo[idx];
+    int64_t idx = e0 * H::GS + v;
+    if (v >= M::E * H::GS || idx >= A.K * H::GS) idx = 0;
+    if constexpr (H::kTG) {
+      h.geo[r] = A.tgeo[idx];
+    } else {
+      h.geo[r] = A.geo[idx];
+    }
   }
 #pragma unroll
   for (int r = 0; r < M::NHE; ++r) {
@@ -324,9 +334,13 @@ void bb_stage_kernel(StageArgs<T> A) {
   __shared__ Pair<T> sfl[TEAMS][E][FB][Nfp];
   __shared__ Pair<T> slev[TEAMS][E][FB][Np];
   __shared__ __attribute__((aligned(16))) T sgeo[TEAMS][E][GEO];
-  // the header staging area is dead once geometry and h_i are derived, so it
-  // shares memory with the lift layers when they are large enough
-  constexpr bool kAliasHg = sizeof(Pair<T>) * FB * Np >= sizeof(double) * kGeoStride;
+  // FP32 groups take the derived geometry (float, computed once on the host)
+  // straight into sgeo; FP64 groups stage the double header and derive it.
+  // The header staging area is dead once geometry and h_i are derived, so it
+  // shares memory with the lift layers when they are large enough.
+  using H = Header<N, T, TW>;
+  static_assert(!H::kTG || GEO == kTGeoStride, "sgeo holds the derived geometry layout");
+  constexpr bool kAliasHg = H::kTG || sizeof(Pair<T>) * FB * Np >= sizeof(double) * kGeoStride;
   __shared__ double shg_own[kAliasHg ? 1 : TEAMS][kAliasHg ? 1 : E * kGeoStride];
   __shared__ int32_t she[TEAMS][E * 4];
   __shared__ uint8_t shf[TEAMS][E * 4];
@@ -450,9 +464,15 @@ void bb_stage_kernel(StageArgs<T> A) {
     // ---- header of this group -> LDS --------------------------------------
     team_sync<TW>();
 #pragma unroll
-    for (int r = 0; r < M::NHG; ++r) {
+    for (int r = 0; r < H::NG; ++r) {
       const int v = lane + TPE * r;
-      if (v < M::HG) shg_w[v] = hd.geo[r];
+      if (v < E * H::GS) {
+        if constexpr (H::kTG) {
+          (&sgeo[w][0][0])[v] = hd.geo[r];
+        } else {
+          shg_w[v] = hd.geo[r];
+        }
+      }
     }
 #pragma unroll
     for (int r = 0; r < M::NHE; ++r) {
@@ -509,8 +529,9 @@ void bb_stage_kernel(StageArgs<T> A) {
     if (g + wstride < g_hi)
       load_header<N, T, TW>(hd, A, kBatch ? (int64_t)__builtin_amdgcn_readfirstlane((uint32_t)(g + wstride) % (uint32_t)G) : g + wstride, lane);
 
-    // ---- per-element derived geometry (one lane per element face) ------------
-    for (int v = lane; v < E * 4; v += TPE) {
+    // ---- per-element derived geometry (one lane per element face; FP32
+    // groups loaded it with the header) -----------------------------------------
+    for (int v = lane; !H::kTG && v < E * 4; v += TPE) {
       const int el = v >> 2;
       const int f = v & 3;
       const double* ge = shg_w + el * kGeoStride;
@@ -546,14 +567,21 @@ void bb_stage_kernel(StageArgs<T> A) {
       if (v < E * Np) {
         const int el = E == 1 ? 0 : v / Np;
         const int n = v - el * Np;
-        // h_i from grad(lambda_i) of the header (double, in LDS since the last sync)
-        const double* hg = shg_w + el * kGeoStride;
         T* hv = hreg[r];
+        if constexpr (H::kTG) {
+          // h_i from grad(lambda_i) of the derived geometry (in LDS since the last sync)
+          const T* gt = sgeo[w][el];
 #pragma unroll
-        for (int i = 1; i < 4; ++i)
-          hv[i] = (T)hg[3 * i - 3] * qv[r][1] + (T)hg[3 * i - 2] * qv[r][2] + (T)hg[3 * i - 1] * qv[r][3];
-        hv[0] = (T)(-(hg[0] + hg[3] + hg[6])) * qv[r][1] + (T)(-(hg[1] + hg[4] + hg[7])) * qv[r][2] +
-                (T)(-(hg[2] + hg[5] + hg[8])) * qv[r][3];
+          for (int i = 0; i < 4; ++i) hv[i] = gt[3 * i] * qv[r][1] + gt[3 * i + 1] * qv[r][2] + gt[3 * i + 2] * qv[r][3];
+        } else {
+          // h_i from grad(lambda_i) of the header (double, in LDS since the last sync)
+          const double* hg = shg_w + el * kGeoStride;
+#pragma unroll
+          for (int i = 1; i < 4; ++i)
+            hv[i] = (T)hg[3 * i - 3] * qv[r][1] + (T)hg[3 * i - 2] * qv[r][2] + (T)hg[3 * i - 1] * qv[r][3];
+          hv[0] = (T)(-(hg[0] + hg[3] + hg[6])) * qv[r][1] + (T)(-(hg[1] + hg[4] + hg[7])) * qv[r][2] +
+                  (T)(-(hg[2] + hg[5] + hg[8])) * qv[r][3];
+        }
         sq_put(el, n, qv[r][0], hv);
       }
     }

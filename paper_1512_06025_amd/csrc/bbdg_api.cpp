@@ -34,6 +34,7 @@ struct bbdg_solver {
   void* d_lift = nullptr;  // nodal: [NpP][Kl]
   void* d_flux = nullptr;  // element-per-thread nodal: face-node fluxes (4, K, 4 Nfp)
   double* d_geo = nullptr;     // K x kGeoStride (see bb_common.hpp)
+  float* d_tgeo = nullptr;     // FP32 Bernstein-Bezier: K x kTGeoStride derived geometry
   int32_t* d_etoe = nullptr;   // K x 4
   uint8_t* d_etofo = nullptr;  // K x 4
   uint16_t* d_tab = nullptr;   // tab_layout(N).size
@@ -200,6 +201,7 @@ template <typename T>
 StageArgs<T> base_args(const bbdg_solver* s, int64_t shots = 1) {
   StageArgs<T> a{};
   a.geo = s->d_geo;
+  if constexpr (sizeof(T) == 4) a.tgeo = s->d_tgeo;
   a.etoe = s->d_etoe;
   a.etofo = s->d_etofo;
   a.tab = s->d_tab;
@@ -448,6 +450,7 @@ NodalArgs<T> nodal_args(const bbdg_solver* s) {
 void free_solver(bbdg_solver* s) {
   if (!s) return;
   if (s->d_geo) (void)hipFree(s->d_geo);
+  if (s->d_tgeo) (void)hipFree(s->d_tgeo);
   if (s->d_etoe) (void)hipFree(s->d_etoe);
   if (s->d_etofo) (void)hipFree(s->d_etofo);
   if (s->d_tab) (void)hipFree(s->d_tab);
@@ -966,6 +969,30 @@ static void device_header(bbdg_solver* s, const double* c, std::vector<double>& 
   }
 }
 
+// The derived geometry of FP32 Bernstein-Bezier solvers (kTGeoStride floats
+// per element, see bb_common.hpp), from the double header: the same double
+// arithmetic the FP64 kernel does per element and stage, rounded once.
+static void derived_geometry_f32(const std::vector<double>& dgeo, int64_t K, std::vector<float>& tgeo) {
+  tgeo.assign((size_t)(kTGeoStride * K), 0.0f);
+  for (int64_t k = 0; k < K; ++k) {
+    const double* ge = dgeo.data() + (size_t)(kGeoStride * k);
+    float* o = tgeo.data() + (size_t)(kTGeoStride * k);
+    for (int f = 0; f < 4; ++f) {
+      double g[3];
+      for (int d = 0; d < 3; ++d) g[d] = f == 0 ? -(ge[d] + ge[3 + d] + ge[6 + d]) : ge[3 * (f - 1) + d];
+      float* fr = o + 16 + 6 * f;
+      for (int d = 0; d < 3; ++d) {
+        o[3 * f + d] = (float)g[d];
+        fr[d] = (float)(-2.0 * g[d]);
+      }
+      fr[3] = (float)ge[10 + f];
+      fr[4] = (float)(0.5 * ge[9]);
+      fr[5] = (float)ge[14 + f];
+    }
+    o[12] = (float)ge[9];
+  }
+}
+
 static int create_impl(bbdg_solver** out, int N, int dtype, int64_t K, const int32_t* EToE, const int8_t* EToF,
                        const int8_t* EToO, const double* geo, const double* c, int bc, int device, int basis) {
   if (!out) return BBDG_E_ARG;
@@ -1007,6 +1034,8 @@ static int create_impl(bbdg_solver** out, int N, int dtype, int64_t K, const int
   for (int64_t k = 0; k < K; ++k) s->h_J[(size_t)k] = geo[10 * k + 9];
   std::vector<double> dgeo;
   device_header(s, c, dgeo);
+  std::vector<float> tgeo;
+  if (dtype == BBDG_F32 && basis == 0) derived_geometry_f32(dgeo, K, tgeo);
   std::vector<uint8_t> fo((size_t)(4 * K));
   for (int64_t slot = 0; slot < 4 * K; ++slot)
     fo[(size_t)slot] = EToE[slot] >= 0 ? (uint8_t)((EToF[slot] & 3) | (EToO[slot] << 2)) : 0;
@@ -1036,6 +1065,10 @@ static int create_impl(bbdg_solver** out, int N, int dtype, int64_t K, const int
             hipMalloc(&s->d_sync, kSyncBytes) == hipSuccess;
   ok = ok && hipMemset(s->d_sync, 0, kSyncBytes) == hipSuccess;
   ok = ok && hipMemcpy(s->d_geo, dgeo.data(), dgeo.size() * sizeof(double), hipMemcpyHostToDevice) == hipSuccess;
+  if (ok && !tgeo.empty()) {
+    ok = hipMalloc(&s->d_tgeo, tgeo.size() * sizeof(float)) == hipSuccess &&
+         hipMemcpy(s->d_tgeo, tgeo.data(), tgeo.size() * sizeof(float), hipMemcpyHostToDevice) == hipSuccess;
+  }
   ok = ok && hipMemcpy(s->d_etoe, EToE, (size_t)(4 * K) * sizeof(int32_t), hipMemcpyHostToDevice) == hipSuccess;
   ok = ok && hipMemcpy(s->d_etofo, fo.data(), fo.size(), hipMemcpyHostToDevice) == hipSuccess;
   ok = ok && hipMemcpy(s->d_tab, tab.data(), tab.size() * sizeof(uint16_t), hipMemcpyHostToDevice) == hipSuccess;
@@ -1364,12 +1397,17 @@ int bbdg_set_wavespeed(bbdg_solver* s, const double* c) {
     if (!(c[k] > 0.0)) return BBDG_E_ARG;
   std::vector<double> dgeo;
   device_header(s, c, dgeo);
+  std::vector<float> tgeo;
+  if (s->d_tgeo) derived_geometry_f32(dgeo, s->K, tgeo);
   // stage records of a misfit run belong to the old wavespeed
   s->rec_work = nullptr;
   s->rec_seg = -1;
   if (hipSetDevice(s->device) != hipSuccess) return BBDG_E_DEVICE;
   if (hipDeviceSynchronize() != hipSuccess) return BBDG_E_DEVICE;
   if (hipMemcpy(s->d_geo, dgeo.data(), dgeo.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+    return BBDG_E_DEVICE;
+  if (s->d_tgeo &&
+      hipMemcpy(s->d_tgeo, tgeo.data(), tgeo.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess)
     return BBDG_E_DEVICE;
   return BBDG_OK;
 }
