@@ -27,6 +27,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "bb_common.hpp"
 #include "bb_launch.hpp"
 
@@ -50,8 +52,6 @@ struct AShape {
   static constexpr int FB = sizeof(T) == 8 ? (N >= 8 ? 1 : (N >= 6 ? 2 : 4)) : (N >= 8 ? 2 : 4);
 
   static constexpr int WPB = (N >= 8) ? 2 : 4;
-  static constexpr int HG = E * kGeoStride;  // header doubles per group
-  static constexpr int NHG = (HG + 63) / 64;
   static constexpr int NHE = (E * 4 + 63) / 64;
   // per element geometry (T): grad lambda_0..3 (12), kappa; per face f at
   // 16 + FS f: g (3), a_p, a_u, b_u, |g|, 1/|g|, -a_p/s, 1/(4|g|) (the
@@ -96,9 +96,14 @@ struct AEll {
 
 // One group's header (per-element geometry, connectivity) held across the
 // previous group's work: lane v keeps header word v.
+// FP32 groups carry the derived geometry (float, computed once on the host);
+// FP64 groups the double header, from which the kernel derives it.
 template <int N, typename T>
 struct AHeader {
-  double geo[AShape<N, T>::NHG];
+  static constexpr bool kTG = sizeof(T) == 4;
+  static constexpr int GS = kTG ? kAGeoStride : kGeoStride;  // header words per element
+  static constexpr int NG = (AShape<N, T>::E * GS + 63) / 64;
+  typename std::conditional<kTG, T, double>::type geo[NG];
   int32_t etoe[AShape<N, T>::NHE];
   uint32_t fo[AShape<N, T>::NHE];
 };
@@ -106,12 +111,17 @@ struct AHeader {
 template <int N, typename T>
 __device__ __forceinline__ void load_aheader(AHeader<N, T>& h, const AdjointArgs<T>& A, int64_t e0, int lane) {
   using S = AShape<N, T>;
+  using H = AHeader<N, T>;
 #pragma unroll
-  for (int r = 0; r < S::NHG; ++r) {
+  for (int r = 0; r < H::NG; ++r) {
     const int v = lane + 64 * r;
-    int64_t idx = e0 * kGeoStride + v;
-    if (v >= S::HG || idx >= A.K * kGeoStride) idx = 0;
-    h.geo[r] = A.geo[idx];
+    int64_t idx = e0 * H::GS + v;
+    if (v >= S::E * H::GS || idx >= A.K * H::GS) idx = 0;
+    if constexpr (H::kTG) {
+      h.geo[r] = A.ageo[idx];
+    } else {
+      h.geo[r] = A.geo[idx];
+    }
   }
 #pragma unroll
   for (int r = 0; r < S::NHE; ++r) {
@@ -157,7 +167,9 @@ void bb_adjoint_kernel(AdjointArgs<T> A) {
   __shared__ T sface[WPB][E][4][3][Nfp];  // per-face node contributions (p, u, tau term)
   __shared__ double sred[WPB][E][5];    // gradient partial sums
   __shared__ T sgeo[WPB][E][GEO];
-  __shared__ double shg[WPB][E * kGeoStride];
+  using H = AHeader<N, T>;
+  static_assert(!H::kTG || GEO == kAGeoStride, "sgeo holds the derived geometry layout");
+  __shared__ double shg[H::kTG ? 1 : WPB][H::kTG ? 1 : E * kGeoStride];  // FP64 header staging
   __shared__ int32_t she[WPB][E * 4];
   __shared__ uint8_t shf[WPB][E * 4];
 
@@ -243,9 +255,15 @@ void bb_adjoint_kernel(AdjointArgs<T> A) {
     // ---- header of this group -> LDS; prefetch the next one -----------------------
     wave_sync();
 #pragma unroll
-    for (int r = 0; r < S::NHG; ++r) {
+    for (int r = 0; r < H::NG; ++r) {
       const int v = lane + 64 * r;
-      if (v < S::HG) shg[w][v] = hd.geo[r];
+      if (v < E * H::GS) {
+        if constexpr (H::kTG) {
+          (&sgeo[w][0][0])[v] = hd.geo[r];
+        } else {
+          shg[H::kTG ? 0 : w][v] = hd.geo[r];
+        }
+      }
     }
 #pragma unroll
     for (int r = 0; r < S::NHE; ++r) {
@@ -316,8 +334,9 @@ void bb_adjoint_kernel(AdjointArgs<T> A) {
       }
     }
 
-    // ---- geometry --------------------------------------------------------------------
-    for (int v = lane; v < E * 4; v += 64) {
+    // ---- geometry (FP64; FP32 groups loaded it with the header; the elements of
+    // a ragged tail then hold element 0's, and nothing of theirs is stored) ----
+    for (int v = lane; !H::kTG && v < E * 4; v += 64) {
       const int el = v >> 2, f = v & 3;
       const int64_t k = e0 + el;
       T* o = sgeo[w][el];
@@ -327,7 +346,7 @@ void bb_adjoint_kernel(AdjointArgs<T> A) {
         for (int c = 0; c < FS; ++c) o[16 + FS * f + c] = 1;
         continue;
       }
-      const double* ge = shg[w] + el * kGeoStride;
+      const double* ge = shg[H::kTG ? 0 : w] + el * kGeoStride;
       double gx, gy, gz;
       if (f == 0) {
         gx = -(ge[0] + ge[3] + ge[6]);

@@ -97,6 +97,7 @@ struct AdjointArgs {
   double* gk;        // (S, K)
   double* gt;        // (S, K, 4)
   const double* geo;
+  const T* ageo;     // FP32: K x kAGeoStride derived geometry (the FP64 kernel derives it from geo)
   const int32_t* etoe;
   const uint8_t* etofo;
   const uint16_t* tab;

@@ -35,6 +35,7 @@ struct bbdg_solver {
   void* d_flux = nullptr;  // element-per-thread nodal: face-node fluxes (4, K, 4 Nfp)
   double* d_geo = nullptr;     // K x kGeoStride (see bb_common.hpp)
   float* d_tgeo = nullptr;     // FP32 Bernstein-Bezier: K x kTGeoStride derived geometry
+  float* d_ageo = nullptr;     // FP32 Bernstein-Bezier: K x kAGeoStride geometry of the reverse stage
   int32_t* d_etoe = nullptr;   // K x 4
   uint8_t* d_etofo = nullptr;  // K x 4
   uint16_t* d_tab = nullptr;   // tab_layout(N).size
@@ -451,6 +452,7 @@ void free_solver(bbdg_solver* s) {
   if (!s) return;
   if (s->d_geo) (void)hipFree(s->d_geo);
   if (s->d_tgeo) (void)hipFree(s->d_tgeo);
+  if (s->d_ageo) (void)hipFree(s->d_ageo);
   if (s->d_etoe) (void)hipFree(s->d_etoe);
   if (s->d_etofo) (void)hipFree(s->d_etofo);
   if (s->d_tab) (void)hipFree(s->d_tab);
@@ -782,6 +784,7 @@ int misfit_typed(bbdg_solver* s, int64_t shots, const T* q0, const int32_t* src_
         ad.gk = gk;
         ad.gt = gt;
         ad.geo = s->d_geo;
+        if constexpr (sizeof(T) == 4) ad.ageo = s->d_ageo;
         ad.etoe = s->d_etoe;
         ad.etofo = s->d_etofo;
         ad.tab = s->d_tab;
@@ -993,6 +996,36 @@ static void derived_geometry_f32(const std::vector<double>& dgeo, int64_t K, std
   }
 }
 
+// The derived geometry of the FP32 reverse stage (kAGeoStride floats per
+// element, see bb_common.hpp), from the double header: the double arithmetic
+// the FP64 reverse stage does per element and stage, rounded once.
+static void derived_adjoint_geometry_f32(const std::vector<double>& dgeo, int64_t K, std::vector<float>& ageo) {
+  constexpr int FS = 12;
+  ageo.assign((size_t)(kAGeoStride * K), 0.0f);
+  for (int64_t k = 0; k < K; ++k) {
+    const double* ge = dgeo.data() + (size_t)(kGeoStride * k);
+    float* o = ageo.data() + (size_t)(kAGeoStride * k);
+    for (int f = 0; f < 4; ++f) {
+      double g[3];
+      for (int d = 0; d < 3; ++d) g[d] = f == 0 ? -(ge[d] + ge[3 + d] + ge[6 + d]) : ge[3 * (f - 1) + d];
+      const double F = 2.0 * std::sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+      float* fr = o + 16 + FS * f;
+      for (int d = 0; d < 3; ++d) {
+        o[3 * f + d] = (float)g[d];
+        fr[d] = (float)(-2.0 * g[d]);
+      }
+      fr[3] = (float)ge[10 + f];
+      fr[4] = (float)(0.5 * ge[9]);
+      fr[5] = (float)ge[14 + f];
+      fr[6] = (float)F;
+      fr[7] = (float)(1.0 / F);
+      fr[8] = (float)(-ge[10 + f] / (4.0 * F * ge[14 + f]));
+      fr[9] = (float)(0.25 / F);
+    }
+    o[12] = (float)ge[9];
+  }
+}
+
 static int create_impl(bbdg_solver** out, int N, int dtype, int64_t K, const int32_t* EToE, const int8_t* EToF,
                        const int8_t* EToO, const double* geo, const double* c, int bc, int device, int basis) {
   if (!out) return BBDG_E_ARG;
@@ -1034,8 +1067,11 @@ static int create_impl(bbdg_solver** out, int N, int dtype, int64_t K, const int
   for (int64_t k = 0; k < K; ++k) s->h_J[(size_t)k] = geo[10 * k + 9];
   std::vector<double> dgeo;
   device_header(s, c, dgeo);
-  std::vector<float> tgeo;
-  if (dtype == BBDG_F32 && basis == 0) derived_geometry_f32(dgeo, K, tgeo);
+  std::vector<float> tgeo, ageo;
+  if (dtype == BBDG_F32 && basis == 0) {
+    derived_geometry_f32(dgeo, K, tgeo);
+    derived_adjoint_geometry_f32(dgeo, K, ageo);
+  }
   std::vector<uint8_t> fo((size_t)(4 * K));
   for (int64_t slot = 0; slot < 4 * K; ++slot)
     fo[(size_t)slot] = EToE[slot] >= 0 ? (uint8_t)((EToF[slot] & 3) | (EToO[slot] << 2)) : 0;
@@ -1067,7 +1103,9 @@ static int create_impl(bbdg_solver** out, int N, int dtype, int64_t K, const int
   ok = ok && hipMemcpy(s->d_geo, dgeo.data(), dgeo.size() * sizeof(double), hipMemcpyHostToDevice) == hipSuccess;
   if (ok && !tgeo.empty()) {
     ok = hipMalloc(&s->d_tgeo, tgeo.size() * sizeof(float)) == hipSuccess &&
-         hipMemcpy(s->d_tgeo, tgeo.data(), tgeo.size() * sizeof(float), hipMemcpyHostToDevice) == hipSuccess;
+         hipMemcpy(s->d_tgeo, tgeo.data(), tgeo.size() * sizeof(float), hipMemcpyHostToDevice) == hipSuccess &&
+         hipMalloc(&s->d_ageo, ageo.size() * sizeof(float)) == hipSuccess &&
+         hipMemcpy(s->d_ageo, ageo.data(), ageo.size() * sizeof(float), hipMemcpyHostToDevice) == hipSuccess;
   }
   ok = ok && hipMemcpy(s->d_etoe, EToE, (size_t)(4 * K) * sizeof(int32_t), hipMemcpyHostToDevice) == hipSuccess;
   ok = ok && hipMemcpy(s->d_etofo, fo.data(), fo.size(), hipMemcpyHostToDevice) == hipSuccess;
@@ -1397,8 +1435,11 @@ int bbdg_set_wavespeed(bbdg_solver* s, const double* c) {
     if (!(c[k] > 0.0)) return BBDG_E_ARG;
   std::vector<double> dgeo;
   device_header(s, c, dgeo);
-  std::vector<float> tgeo;
-  if (s->d_tgeo) derived_geometry_f32(dgeo, s->K, tgeo);
+  std::vector<float> tgeo, ageo;
+  if (s->d_tgeo) {
+    derived_geometry_f32(dgeo, s->K, tgeo);
+    derived_adjoint_geometry_f32(dgeo, s->K, ageo);
+  }
   // stage records of a misfit run belong to the old wavespeed
   s->rec_work = nullptr;
   s->rec_seg = -1;
@@ -1407,7 +1448,8 @@ int bbdg_set_wavespeed(bbdg_solver* s, const double* c) {
   if (hipMemcpy(s->d_geo, dgeo.data(), dgeo.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
     return BBDG_E_DEVICE;
   if (s->d_tgeo &&
-      hipMemcpy(s->d_tgeo, tgeo.data(), tgeo.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess)
+      (hipMemcpy(s->d_tgeo, tgeo.data(), tgeo.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
+       hipMemcpy(s->d_ageo, ageo.data(), ageo.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess))
     return BBDG_E_DEVICE;
   return BBDG_OK;
 }
