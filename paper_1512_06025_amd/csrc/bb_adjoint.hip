@@ -42,6 +42,33 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
+// A double moved between lanes by a DPP lane pattern (two 32-bit halves).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double x) {
+  const long long v = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(v & 0xffffffffLL), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(v >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// Sum over each row of 16 lanes, left in every lane of the row: pairs and
+// quads (quad_perm [1,0,3,2], [2,3,0,1]), then half rows (row_half_mirror)
+// and rows (row_mirror).  Vector instructions only, no LDS round trip.
+__device__ __forceinline__ double row_sum16(double t) {
+  t += dpp_f64<0xB1>(t);
+  t += dpp_f64<0x4E>(t);
+  t += dpp_f64<0x141>(t);
+  t += dpp_f64<0x140>(t);
+  return t;
+}
+
+__device__ __forceinline__ double lane_f64(double x, int l) {
+  const long long v = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)(v & 0xffffffffLL), l);
+  const int hi = __builtin_amdgcn_readlane((int)(v >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
 template <int N, typename T>
 struct AShape {
   static constexpr int Np = np_of(N);
@@ -142,10 +169,11 @@ void bb_adjoint_kernel(AdjointArgs<T> A) {
   constexpr int Np = S::Np, Nfp = S::Nfp, E = S::E, NPL = S::NPL, NFI = S::NFI;
   constexpr int FB = S::FB, WPB = S::WPB, GEO = S::GEO, FS = S::FS;
   constexpr TabLayout L = tab_layout(N);
-  // Per-element gradient sums: in FP64 (fewer waves per SIMD) shuffle
-  // butterflies are faster; in FP32 independent LDS reads feeding one add
-  // chain beat the butterfly's dependent LDS round trips.
-  constexpr bool kShuffleSums = E == 1 && sizeof(T) == 8;
+  // Per-element gradient sums (FP64) with one element per wave: row sums by
+  // DPP lane permutes, vector instructions only (measured faster in FP32
+  // than one lane adding the values serially, and in FP64 than butterflies
+  // through LDS permutes); several elements per wave add serially.
+  constexpr bool kShuffleSums = E == 1;
 
   __shared__ uint16_t t_fnode[4 * Nfp];
   __shared__ uint16_t t_fperm[6 * Nfp];
@@ -577,13 +605,12 @@ void bb_adjoint_kernel(AdjointArgs<T> A) {
       }
     }
     if constexpr (kShuffleSums) {
-      // tau terms of the four faces (kept in sface by every batch): 16 lanes
-      // per face, then a butterfly over the 16
+      // tau terms of the four faces (kept in sface by every batch): one row
+      // of 16 lanes per face
       const int f = lane >> 4, j = lane & 15;
       double t = 0.0;
       for (int gg = j; gg < Nfp; gg += 16) t += (double)sface[w][0][f][2][gg];
-#pragma unroll
-      for (int m = 8; m >= 1; m >>= 1) t += __shfl_xor(t, m);
+      t = row_sum16(t);
       if (j == 0) sred[w][0][1 + f] = t;
     }
 
@@ -613,8 +640,8 @@ void bb_adjoint_kernel(AdjointArgs<T> A) {
       double t = 0.0;  // lanes past the element hold zeros
 #pragma unroll
       for (int r = 0; r < NPL; ++r) t += (double)kpart[r];
-#pragma unroll
-      for (int m = 32; m >= 1; m >>= 1) t += __shfl_xor(t, m);
+      t = row_sum16(t);
+      t = (lane_f64(t, 0) + lane_f64(t, 16)) + (lane_f64(t, 32) + lane_f64(t, 48));
       if (lane == 0) sred[w][0][0] = t;
     } else {
 #pragma unroll
