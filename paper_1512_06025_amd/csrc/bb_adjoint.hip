@@ -69,13 +69,27 @@ __device__ __forceinline__ double lane_f64(double x, int l) {
   return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
+// position stride of the lift items: the next power of two when that costs
+// no extra pass over the 64 lanes (decoding then needs shifts only)
+__host__ __device__ constexpr int a_pow2ceil(int x) {
+  int p = 1;
+  while (p < x) p *= 2;
+  return p;
+}
+__host__ __device__ constexpr int a_item_stride(int cnt, int groups) {
+  return (groups * a_pow2ceil(cnt) + 63) / 64 == (groups * cnt + 63) / 64 ? a_pow2ceil(cnt) : cnt;
+}
+
 template <int N, typename T>
 struct AShape {
   static constexpr int Np = np_of(N);
   static constexpr int Nfp = nfp_of(N);
   static constexpr int E = (Np <= 32) ? (64 / Np) : 1;
   static constexpr int NPL = (E * Np + 63) / 64;
-  static constexpr int NFI = (E * 4 * Nfp + 63) / 64;
+  // face items (element, face, position) over the 64 lanes, positions strided
+  // by SF (a power of two where that costs no extra pass)
+  static constexpr int SF = a_item_stride(Nfp, E * 4);
+  static constexpr int NFI = (E * 4 * SF + 63) / 64;
   static constexpr int FB = sizeof(T) == 8 ? (N >= 8 ? 1 : (N >= 6 ? 2 : 4)) : (N >= 8 ? 2 : 4);
 
   static constexpr int WPB = (N >= 8) ? 2 : 4;
@@ -91,17 +105,6 @@ template <typename T>
 struct alignas(2 * sizeof(T)) APair {
   T p, u;
 };
-
-// position stride of the lift items: the next power of two when that costs
-// no extra pass over the 64 lanes (decoding then needs shifts only)
-__host__ __device__ constexpr int a_pow2ceil(int x) {
-  int p = 1;
-  while (p < x) p *= 2;
-  return p;
-}
-__host__ __device__ constexpr int a_item_stride(int cnt, int groups) {
-  return (groups * a_pow2ceil(cnt) + 63) / 64 == (groups * cnt + 63) / 64 ? a_pow2ceil(cnt) : cnt;
-}
 
 // occupancy target (waves per SIMD) bounding the register allocation
 template <int N, typename T>
@@ -257,6 +260,15 @@ void bb_adjoint_kernel(AdjointArgs<T> A) {
 
   const int lane0 = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  // face item r of lane ln: element el, face f, position gg (false: none)
+  auto face_item = [&](int ln, int r, int& el, int& f, int& gg) -> bool {
+    const unsigned v = (unsigned)ln + 64u * (unsigned)r;
+    const unsigned q = v / S::SF;  // el * 4 + f
+    gg = (int)(v % S::SF);
+    f = (int)(q & 3);
+    el = (int)(q >> 2);
+    return el < E && gg < Nfp;
+  };
   const int64_t K = A.K;
   const int64_t KNp = K * Np;
   const int64_t G = (K + E - 1) / E;
@@ -328,13 +340,9 @@ void bb_adjoint_kernel(AdjointArgs<T> A) {
     T zq[NFI][2], rjv[NFI][2];
 #pragma unroll
     for (int r = 0; r < NFI; ++r) {
-      const int v = lane + 64 * r;
       zq[r][0] = zq[r][1] = rjv[r][0] = rjv[r][1] = 0;
-      if (v >= E * 4 * Nfp) continue;
-      const int el = E == 1 ? 0 : v / (4 * Nfp);
-      const int rem = v - el * 4 * Nfp;
-      const int f = rem / Nfp;
-      const int gg = rem - f * Nfp;
+      int el, f, gg;
+      if (!face_item(lane, r, el, f, gg)) continue;
       const int64_t k = e0 + el;
       if (k >= K) continue;
       const T* rj = A.rec_j + (shot * K + k) * 8 * Nfp + f * 2 * Nfp + gg;
@@ -409,12 +417,8 @@ void bb_adjoint_kernel(AdjointArgs<T> A) {
     if (A.pull) {
 #pragma unroll
       for (int r = 0; r < NFI; ++r) {
-        const int v = lane + 64 * r;
-        if (v >= E * 4 * Nfp) continue;
-        const int el = E == 1 ? 0 : v / (4 * Nfp);
-        const int rem = v - el * 4 * Nfp;
-        const int f = rem / Nfp;
-        const int gg = rem - f * Nfp;
+        int el, f, gg;
+        if (!face_item(lane, r, el, f, gg)) continue;
         // the neighbour's g is -(|g_nb|/|g_f|) g_f and zu carries |g_nb|:
         // the velocity adjoint gains -(g_f/|g_f|) zu
         sface[w][el][f][0][gg] = zq[r][0];
@@ -558,13 +562,8 @@ void bb_adjoint_kernel(AdjointArgs<T> A) {
       // transposed flux on the face nodes of this batch
 #pragma unroll
       for (int r = 0; r < NFI; ++r) {
-        const int v = lane + 64 * r;
-        if (v >= E * 4 * Nfp) continue;
-        const int el = E == 1 ? 0 : v / (4 * Nfp);
-        const int rem = v - el * 4 * Nfp;
-        const int f = rem / Nfp;
-        const int gg = rem - f * Nfp;
-        if (f < fb0 || f >= fb0 + FB) continue;
+        int el, f, gg;
+        if (!face_item(lane, r, el, f, gg) || f < fb0 || f >= fb0 + FB) continue;
         const int64_t k = e0 + el;
         T dp = 0, du = 0, tau = 0;
         if (k < K) {
