@@ -291,6 +291,14 @@ void bb_adjoint_kernel(AdjointArgs<T> A) {
     const int64_t e0 = (g - shot * G) * E;
     const int64_t sb = shot * 4 * KNp;
     const int64_t zb = shot * K * 8 * Nfp;
+    // this shot's arrays (uniform bases; in-shot offsets fit in 32 bits:
+    // 4 K Np < 2^31 and 8 K Nfp < 2^32 for every order)
+    T* const qb_s = A.qb + sb;
+    T* const rb_s = A.rb + sb;
+    const T* const recp_s = A.rec_p + shot * KNp;
+    const T* const recj_s = A.rec_j + zb;
+    const T* const zin_s = A.z_in + zb;
+    T* const zout_s = A.z_out + zb;
 
     // ---- header of this group -> LDS; prefetch the next one -----------------------
     wave_sync();
@@ -328,13 +336,18 @@ void bb_adjoint_kernel(AdjointArgs<T> A) {
       const int el = E == 1 ? 0 : v / Np;
       const int n = v - el * Np;
       const bool ok = (v < E * Np) && (e0 + el < K);
+      // (lanes without a node read element 0 of the shot and discard it)
       noff[r] = ok ? (uint32_t)((e0 + el) * 4 * Np + n) : 0u;
+      const T* qp = qb_s + noff[r];
+      const T* up = rb_s + noff[r];
 #pragma unroll
       for (int f = 0; f < 4; ++f) {
-        qv[r][f] = ok ? A.qb[sb + f * Np + noff[r]] : (T)0;
-        uv[r][f] = ok ? A.rb[sb + f * Np + noff[r]] : (T)0;
+        const T x = qp[f * Np], y = up[f * Np];
+        qv[r][f] = ok ? x : (T)0;
+        uv[r][f] = ok ? y : (T)0;
       }
-      pv[r] = ok ? A.rec_p[shot * KNp + (e0 + el) * Np + n] : (T)0;
+      const T pr = recp_s[ok ? (uint32_t)((e0 + el) * Np + n) : 0u];
+      pv[r] = ok ? pr : (T)0;
     }
     // per face item: the neighbour's face adjoint (pull) and the recorded jumps
     T zq[NFI][2], rjv[NFI][2];
@@ -345,14 +358,14 @@ void bb_adjoint_kernel(AdjointArgs<T> A) {
       if (!face_item(lane, r, el, f, gg)) continue;
       const int64_t k = e0 + el;
       if (k >= K) continue;
-      const T* rj = A.rec_j + (shot * K + k) * 8 * Nfp + f * 2 * Nfp + gg;
+      const T* rj = recj_s + ((uint32_t)k * (8 * Nfp) + f * 2 * Nfp + gg);
       rjv[r][0] = rj[0];
       rjv[r][1] = rj[Nfp];
       const int nb = she[w][el * 4 + f];
       if (A.pull && nb >= 0) {
         const int info = shf[w][el * 4 + f];
         const int g2 = t_fperm[(info >> 2) * Nfp + gg];
-        const T* zs = A.z_in + zb + ((int64_t)nb * 4 + (info & 3)) * 2 * Nfp + g2;
+        const T* zs = zin_s + (((uint32_t)nb * 4 + (info & 3)) * (2 * Nfp) + g2);
         zq[r][0] = zs[0];
         zq[r][1] = zs[Nfp];
       }
@@ -573,7 +586,7 @@ void bb_adjoint_kernel(AdjointArgs<T> A) {
           // sp = a_p [[p]] - a_u g.[[u]],  su = b_u g.[[u]] - [[p]]/2
           const T jbp = fr[3] * zp - (T)0.5 * zu;
           const T jbg = fr[5] * zu - fr[4] * zp;
-          T* zo = A.z_out + zb + (k * 4 + f) * 2 * Nfp + gg;
+          T* zo = zout_s + (((uint32_t)k * 4 + f) * (2 * Nfp) + gg);
           zo[0] = jbp;
           zo[Nfp] = fr[6] * jbg;
           const int nb = she[w][el * 4 + f];
@@ -678,10 +691,12 @@ void bb_adjoint_kernel(AdjointArgs<T> A) {
       const int v = lane + 64 * r;
       const int el = E == 1 ? 0 : v / Np;
       if (v >= E * Np || e0 + el >= K) continue;
+      T* const qo = qb_s + noff[r];
+      T* const ro = rb_s + noff[r];
 #pragma unroll
       for (int f = 0; f < 4; ++f) {
-        A.qb[sb + f * Np + noff[r]] = qv[r][f] + dt * acc[r][f];
-        A.rb[sb + f * Np + noff[r]] = a_s * uv[r][f];
+        qo[f * Np] = qv[r][f] + dt * acc[r][f];
+        ro[f * Np] = a_s * uv[r][f];
       }
     }
   }
