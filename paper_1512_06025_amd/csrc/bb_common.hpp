@@ -30,8 +30,9 @@ constexpr int level_off(int j, int N) { return np_of(N) - np_of(N - j); }
 // element's own c on boundary faces).
 constexpr int kGeoStride = 18;
 
-// Derived per-element geometry of FP32 Bernstein-Bezier solvers (float),
-// computed once on the host in double from the header above and rounded:
+// Derived per-element geometry of Bernstein-Bezier solvers in the element
+// type, computed once on the host in double from the header above (rounded
+// once in FP32):
 // grad lambda_0..3 (12 values; lambda_0 = 1 - lambda_1 - lambda_2 - lambda_3),
 // kappa, 3 zeros, then for each face f at 16 + 6 f: g_f = -2 grad(lambda_f)
 // (3 values), a_p, kappa / 2, b_u.

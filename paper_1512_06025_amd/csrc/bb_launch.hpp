@@ -14,7 +14,7 @@ struct StageArgs {
   T* qout;
   T* res;
   const double* geo;      // K x kGeoStride
-  const T* tgeo;          // FP32: K x kTGeoStride derived geometry (the FP64 kernel derives it from geo)
+  const T* tgeo;          // K x kTGeoStride derived geometry (FP64 groups of several elements derive it from geo)
   const int32_t* etoe;    // K x 4, -1 on the boundary
   const uint8_t* etofo;   // K x 4: neighbour face | orientation << 2
   const uint16_t* tab;    // index tables of the order

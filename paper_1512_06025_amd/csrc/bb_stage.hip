@@ -162,11 +162,18 @@ struct Ell {
 };
 
 // Header of an element group in registers (prefetched one group ahead): the
-// double geometry (FP64, derived per element in the kernel) or the derived
-// geometry in float (FP32, computed once on the host), and the connectivity.
+// per-element derived geometry in the element type, computed once on the
+// host (kTGeoStride values), or, in FP64 where that larger header would take
+// more registers per lane (element groups of 3, 7 or more elements), the
+// double header from which the kernel derives it; and the connectivity.
+// (Measured on 196,608 tets in FP64: the derived header is 1-2 % faster at
+// N = 5..9 and 7 % on the cache-resident 24,576-tet mesh at N = 5, but 2 %
+// slower at N = 4, whose seven-element groups need a second register.)
 template <int N, typename T, int TW>
 struct Header {
-  static constexpr bool kTG = sizeof(T) == 4;
+  static constexpr int NGT = (Team<N, T, TW>::E * kTGeoStride + Team<N, T, TW>::TPE - 1) / Team<N, T, TW>::TPE;
+  static constexpr int NGD = (Team<N, T, TW>::E * kGeoStride + Team<N, T, TW>::TPE - 1) / Team<N, T, TW>::TPE;
+  static constexpr bool kTG = sizeof(T) == 4 || NGT == NGD;
   static constexpr int GS = kTG ? kTGeoStride : kGeoStride;  // header words per element
   static constexpr int NG = (Team<N, T, TW>::E * GS + Team<N, T, TW>::TPE - 1) / Team<N, T, TW>::TPE;
   typename std::conditional<kTG, T, double>::type geo[NG];

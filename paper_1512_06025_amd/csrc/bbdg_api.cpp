@@ -35,6 +35,7 @@ struct bbdg_solver {
   void* d_flux = nullptr;  // element-per-thread nodal: face-node fluxes (4, K, 4 Nfp)
   double* d_geo = nullptr;     // K x kGeoStride (see bb_common.hpp)
   float* d_tgeo = nullptr;     // FP32 Bernstein-Bezier: K x kTGeoStride derived geometry
+  double* d_tgeo64 = nullptr;  // FP64 Bernstein-Bezier: the same in double
   float* d_ageo = nullptr;     // FP32 Bernstein-Bezier: K x kAGeoStride geometry of the reverse stage
   int32_t* d_etoe = nullptr;   // K x 4
   uint8_t* d_etofo = nullptr;  // K x 4
@@ -202,7 +203,11 @@ template <typename T>
 StageArgs<T> base_args(const bbdg_solver* s, int64_t shots = 1) {
   StageArgs<T> a{};
   a.geo = s->d_geo;
-  if constexpr (sizeof(T) == 4) a.tgeo = s->d_tgeo;
+  if constexpr (sizeof(T) == 4) {
+    a.tgeo = s->d_tgeo;
+  } else {
+    a.tgeo = s->d_tgeo64;
+  }
   a.etoe = s->d_etoe;
   a.etofo = s->d_etofo;
   a.tab = s->d_tab;
@@ -452,6 +457,7 @@ void free_solver(bbdg_solver* s) {
   if (!s) return;
   if (s->d_geo) (void)hipFree(s->d_geo);
   if (s->d_tgeo) (void)hipFree(s->d_tgeo);
+  if (s->d_tgeo64) (void)hipFree(s->d_tgeo64);
   if (s->d_ageo) (void)hipFree(s->d_ageo);
   if (s->d_etoe) (void)hipFree(s->d_etoe);
   if (s->d_etofo) (void)hipFree(s->d_etofo);
@@ -972,29 +978,32 @@ static void device_header(bbdg_solver* s, const double* c, std::vector<double>& 
   }
 }
 
-// The derived geometry of FP32 Bernstein-Bezier solvers (kTGeoStride floats
-// per element, see bb_common.hpp), from the double header: the same double
-// arithmetic the FP64 kernel does per element and stage, rounded once.
-static void derived_geometry_f32(const std::vector<double>& dgeo, int64_t K, std::vector<float>& tgeo) {
-  tgeo.assign((size_t)(kTGeoStride * K), 0.0f);
+// The derived geometry of Bernstein-Bezier solvers (kTGeoStride values per
+// element, see bb_common.hpp), from the double header: the double arithmetic
+// the kernel otherwise does per element and stage, rounded once in FP32.
+extern "C++" {
+template <typename F>
+static void derived_geometry(const std::vector<double>& dgeo, int64_t K, std::vector<F>& tgeo) {
+  tgeo.assign((size_t)(kTGeoStride * K), (F)0);
   for (int64_t k = 0; k < K; ++k) {
     const double* ge = dgeo.data() + (size_t)(kGeoStride * k);
-    float* o = tgeo.data() + (size_t)(kTGeoStride * k);
+    F* o = tgeo.data() + (size_t)(kTGeoStride * k);
     for (int f = 0; f < 4; ++f) {
       double g[3];
       for (int d = 0; d < 3; ++d) g[d] = f == 0 ? -(ge[d] + ge[3 + d] + ge[6 + d]) : ge[3 * (f - 1) + d];
-      float* fr = o + 16 + 6 * f;
+      F* fr = o + 16 + 6 * f;
       for (int d = 0; d < 3; ++d) {
-        o[3 * f + d] = (float)g[d];
-        fr[d] = (float)(-2.0 * g[d]);
+        o[3 * f + d] = (F)g[d];
+        fr[d] = (F)(-2.0 * g[d]);
       }
-      fr[3] = (float)ge[10 + f];
-      fr[4] = (float)(0.5 * ge[9]);
-      fr[5] = (float)ge[14 + f];
+      fr[3] = (F)ge[10 + f];
+      fr[4] = (F)(0.5 * ge[9]);
+      fr[5] = (F)ge[14 + f];
     }
-    o[12] = (float)ge[9];
+    o[12] = (F)ge[9];
   }
 }
+}  // extern "C++"
 
 // The derived geometry of the FP32 reverse stage (kAGeoStride floats per
 // element, see bb_common.hpp), from the double header: the double arithmetic
@@ -1068,8 +1077,10 @@ static int create_impl(bbdg_solver** out, int N, int dtype, int64_t K, const int
   std::vector<double> dgeo;
   device_header(s, c, dgeo);
   std::vector<float> tgeo, ageo;
+  std::vector<double> tgeo64;
+  if (dtype == BBDG_F64 && basis == 0) derived_geometry<double>(dgeo, K, tgeo64);
   if (dtype == BBDG_F32 && basis == 0) {
-    derived_geometry_f32(dgeo, K, tgeo);
+    derived_geometry<float>(dgeo, K, tgeo);
     derived_adjoint_geometry_f32(dgeo, K, ageo);
   }
   std::vector<uint8_t> fo((size_t)(4 * K));
@@ -1101,6 +1112,10 @@ static int create_impl(bbdg_solver** out, int N, int dtype, int64_t K, const int
             hipMalloc(&s->d_sync, kSyncBytes) == hipSuccess;
   ok = ok && hipMemset(s->d_sync, 0, kSyncBytes) == hipSuccess;
   ok = ok && hipMemcpy(s->d_geo, dgeo.data(), dgeo.size() * sizeof(double), hipMemcpyHostToDevice) == hipSuccess;
+  if (ok && !tgeo64.empty()) {
+    ok = hipMalloc(&s->d_tgeo64, tgeo64.size() * sizeof(double)) == hipSuccess &&
+         hipMemcpy(s->d_tgeo64, tgeo64.data(), tgeo64.size() * sizeof(double), hipMemcpyHostToDevice) == hipSuccess;
+  }
   if (ok && !tgeo.empty()) {
     ok = hipMalloc(&s->d_tgeo, tgeo.size() * sizeof(float)) == hipSuccess &&
          hipMemcpy(s->d_tgeo, tgeo.data(), tgeo.size() * sizeof(float), hipMemcpyHostToDevice) == hipSuccess &&
@@ -1435,9 +1450,11 @@ int bbdg_set_wavespeed(bbdg_solver* s, const double* c) {
     if (!(c[k] > 0.0)) return BBDG_E_ARG;
   std::vector<double> dgeo;
   device_header(s, c, dgeo);
+  std::vector<double> tgeo64;
+  if (s->d_tgeo64) derived_geometry<double>(dgeo, s->K, tgeo64);
   std::vector<float> tgeo, ageo;
   if (s->d_tgeo) {
-    derived_geometry_f32(dgeo, s->K, tgeo);
+    derived_geometry<float>(dgeo, s->K, tgeo);
     derived_adjoint_geometry_f32(dgeo, s->K, ageo);
   }
   // stage records of a misfit run belong to the old wavespeed
@@ -1446,6 +1463,9 @@ int bbdg_set_wavespeed(bbdg_solver* s, const double* c) {
   if (hipSetDevice(s->device) != hipSuccess) return BBDG_E_DEVICE;
   if (hipDeviceSynchronize() != hipSuccess) return BBDG_E_DEVICE;
   if (hipMemcpy(s->d_geo, dgeo.data(), dgeo.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+    return BBDG_E_DEVICE;
+  if (s->d_tgeo64 &&
+      hipMemcpy(s->d_tgeo64, tgeo64.data(), tgeo64.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
     return BBDG_E_DEVICE;
   if (s->d_tgeo &&
       (hipMemcpy(s->d_tgeo, tgeo.data(), tgeo.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
