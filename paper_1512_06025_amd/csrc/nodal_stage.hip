@@ -15,7 +15,8 @@
 // rows padded to NC + 16 so that the 16 x 4 operand reads are free of bank
 // conflicts), and whose A operands (the operators, shared by every block)
 // come from L1/L2; every A tile a wave loads feeds the MFMAs of its column
-// tiles.  The waves split the 16-row tiles of the output (and, where there
+// tiles, and in FP64 (and FP32 at N = 9) the A values of the next chunk of
+// k-steps are loaded into registers while the current chunk's MFMAs run.  The waves split the 16-row tiles of the output (and, where there
 // are fewer row tiles than waves, the column tiles).
 //   1. Stage the block's nodal values X (Kv x NC) in LDS.
 //   2. Volume: for i = 1..3, Y_i = Dr_i X by MFMA, then the geometric
@@ -83,6 +84,61 @@ __device__ __forceinline__ double quad_perm(double x) {
 constexpr int kQuadBcast0 = 0x00;  // every lane of the quad reads lane 0
 constexpr int kQuadSwap1 = 0xB1;   // (1, 0, 3, 2)
 constexpr int kQuadSwap2 = 0x4E;   // (2, 3, 0, 1)
+
+// Applies NOPS operators, each a 16-row slice of a dense matrix in global
+// memory (K columns, operator o at a_ptr + o op_stride; this lane's row and
+// k offset already in a_ptr), to the block's B operand in LDS (b already at
+// this lane's k row, b[k0 ncp + 16 ct + bcol] the column tiles): y = A_o B
+// on CTW column tiles, then done(o, y).  The A values of a chunk of up to 8
+// (FP64) or 16 (FP32) k-steps sit in registers, and the next chunk's loads (the next operator's
+// first chunk included) are issued before the current chunk's MFMAs, so the
+// L2 latency of the operator reads overlaps the matrix work.
+template <int NOPS, int K, int CTW, typename M, typename T, typename Done>
+__device__ __forceinline__ void mfma_ops(const T* __restrict__ a_ptr, size_t op_stride, const T* b, int ncp,
+                                         int bcol, Done&& done) {
+  typedef typename M::acc acc_t;
+  constexpr int KCM = sizeof(T) == 8 ? 8 : 16;  // k-steps per chunk (registers: 2 KCM values)
+  constexpr int KS = K / 4, KC = KS < KCM ? KS : KCM, NCH = (KS + KC - 1) / KC, NQ = NOPS * NCH;
+  T a0[KC], a1[KC];
+  auto load = [&](T (&dst)[KC], int q) {
+    const int o = q / NCH, ch = q % NCH;
+    const T* p = a_ptr + (size_t)o * op_stride + ch * KC * 4;
+#pragma unroll
+    for (int kk = 0; kk < KC; ++kk)
+      if (ch * KC + kk < KS) dst[kk] = p[kk * 4];
+  };
+  load(a0, 0);
+  acc_t y[CTW];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int o = q / NCH, ch = q % NCH;
+    if (ch == 0) {
+#pragma unroll
+      for (int ct = 0; ct < CTW; ++ct) y[ct] = M::zero();
+    }
+    if (q + 1 < NQ) {
+      if (q & 1) {
+        load(a0, q + 1);
+      } else {
+        load(a1, q + 1);
+      }
+    }
+    const T(&cur)[KC] = (q & 1) ? a1 : a0;
+#pragma unroll
+    for (int kk = 0; kk < KC; ++kk) {
+      const int ks = ch * KC + kk;
+      if (ks >= KS) break;
+#pragma unroll
+      for (int ct = 0; ct < CTW; ++ct) y[ct] = M::mac(cur[kk], b[ks * 4 * ncp + ct * 16 + bcol], y[ct]);
+    }
+    if (ch == NCH - 1) {
+      done(o, y);
+      // keep the next operator's LDS reads from being hoisted above this
+      // point (registers); its first A chunk is already in flight
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+}
 
 }  // namespace
 
@@ -178,39 +234,53 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void n
     for (int ct = 0; ct < CTW; ++ct) rhs[r][ct] = M::zero();
 
   // ---- volume: Y_i = Dr_i X, combined with grad(lambda_i) per element ---------------
+  // (FP64 and FP32 at N = 9: operator reads software-pipelined through
+  // registers, mfma_ops; FP32 below: one operator at a time, A read per
+  // k-step, which keeps the register count and the occupancy up.  Measured on
+  // 196,608 tets: the pipeline is 2-10 % faster in FP64 at N = 3..7 and 4 %
+  // in FP32 at N = 9, but 2-6 % slower in FP32 at N = 3..7.)
+  constexpr bool kPipe = sizeof(T) == 8 || N >= 9;
+  auto combine = [&](int r, int i, acc_t(&y)[CTW]) {
+#pragma unroll
+    for (int ct = 0; ct < CTW; ++ct) {
+      const int el = (c0 + ct) * 4 + (ri >> 2);
+      // d(lambda_{i+1})/d(x_{fl-1}) on velocity lanes, 0 on pressure lanes
+      const T gc = fl ? (T)shg[el * kGeoStride + 3 * i + fl - 1] : (T)0;
+      const T kap = (T)shg[el * kGeoStride + 9];
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) {
+        const T yv = y[ct][rr];
+        const T p = quad_perm<kQuadBcast0>(yv);
+        T s = gc * yv;
+        s += quad_perm<kQuadSwap1>(s);
+        s += quad_perm<kQuadSwap2>(s);
+        rhs[r][ct][rr] -= fl ? gc * p : kap * s;
+      }
+    }
+  };
   if constexpr (kVol) {
 #pragma unroll
     for (int r = 0; r < RPW; ++r) {
       const int rt = wr + WR * r;
       if (rt >= MT || !cols) break;
+      if constexpr (kPipe) {
+        mfma_ops<3, Kv, CTW, M>(A.dr + (size_t)(rt * 16 + ri) * Kv + kq, (size_t)NpP * Kv, buf + kq * NCP, NCP,
+                                c0 * 16 + ri, [&](int i, acc_t(&y)[CTW]) { combine(r, i, y); });
+      } else {
 #pragma unroll 1
-      for (int i = 0; i < 3; ++i) {
-        acc_t y[CTW];
+        for (int i = 0; i < 3; ++i) {
+          acc_t y[CTW];
 #pragma unroll
-        for (int ct = 0; ct < CTW; ++ct) y[ct] = M::zero();
-        const T* Ai = A.dr + (size_t)i * NpP * Kv + (size_t)(rt * 16 + ri) * Kv + kq;
+          for (int ct = 0; ct < CTW; ++ct) y[ct] = M::zero();
+          const T* Ai = A.dr + (size_t)i * NpP * Kv + (size_t)(rt * 16 + ri) * Kv + kq;
 #pragma unroll 4
-        for (int k0 = 0; k0 < Kv; k0 += 4) {
-          const T a = Ai[k0];
+          for (int k0 = 0; k0 < Kv; k0 += 4) {
+            const T a = Ai[k0];
 #pragma unroll
-          for (int ct = 0; ct < CTW; ++ct)
-            y[ct] = M::mac(a, buf[(k0 + kq) * NCP + (c0 + ct) * 16 + ri], y[ct]);
-        }
-#pragma unroll
-        for (int ct = 0; ct < CTW; ++ct) {
-          const int el = (c0 + ct) * 4 + (ri >> 2);
-          // d(lambda_{i+1})/d(x_{fl-1}) on velocity lanes, 0 on pressure lanes
-          const T gc = fl ? (T)shg[el * kGeoStride + 3 * i + fl - 1] : (T)0;
-          const T kap = (T)shg[el * kGeoStride + 9];
-#pragma unroll
-          for (int rr = 0; rr < 4; ++rr) {
-            const T yv = y[ct][rr];
-            const T p = quad_perm<kQuadBcast0>(yv);
-            T s = gc * yv;
-            s += quad_perm<kQuadSwap1>(s);
-            s += quad_perm<kQuadSwap2>(s);
-            rhs[r][ct][rr] -= fl ? gc * p : kap * s;
+            for (int ct = 0; ct < CTW; ++ct)
+              y[ct] = M::mac(a, buf[(k0 + kq) * NCP + (c0 + ct) * 16 + ri], y[ct]);
           }
+          combine(r, i, y);
         }
       }
     }
@@ -282,13 +352,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void n
     for (int r = 0; r < RPW; ++r) {
       const int rt = wr + WR * r;
       if (rt >= MT || !cols) break;
-      const T* Lr = A.lift + (size_t)(rt * 16 + ri) * Kl + kq;
-#pragma unroll 4
-      for (int k0 = 0; k0 < Kl; k0 += 4) {
-        const T a = Lr[k0];
+      if constexpr (kPipe) {
+        mfma_ops<1, Kl, CTW, M>(A.lift + (size_t)(rt * 16 + ri) * Kl + kq, 0, buf + kq * NCP, NCP, c0 * 16 + ri,
+                                [&](int, acc_t(&y)[CTW]) {
 #pragma unroll
-        for (int ct = 0; ct < CTW; ++ct)
-          rhs[r][ct] = M::mac(a, buf[(k0 + kq) * NCP + (c0 + ct) * 16 + ri], rhs[r][ct]);
+          for (int ct = 0; ct < CTW; ++ct) rhs[r][ct] += y[ct];
+        });
+      } else {
+        const T* Lr = A.lift + (size_t)(rt * 16 + ri) * Kl + kq;
+#pragma unroll 4
+        for (int k0 = 0; k0 < Kl; k0 += 4) {
+          const T a = Lr[k0];
+#pragma unroll
+          for (int ct = 0; ct < CTW; ++ct)
+            rhs[r][ct] = M::mac(a, buf[(k0 + kq) * NCP + (c0 + ct) * 16 + ri], rhs[r][ct]);
+        }
       }
     }
   }
