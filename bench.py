@@ -421,7 +421,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py: this solver runs on a single GPU; multi-GPU runs (--gpus %d) are not "
-              "supported by this build" % args.gpus, file=sys.stderr)
+              "supported" % args.gpus, file=sys.stderr)
         sys.exit(2)
     legs = set(x for x in args.legs.split(",") if x) - set(l for l in LEGS if getattr(args, "skip_" + l))
 

@@ -100,8 +100,7 @@ def load():
     if _lib is not None:
         return _lib
     if not os.path.exists(LIB_PATH):
-        raise ImportError("libbbdg.so is not built (run __graft_entry__.build() or "
-                          "python paper_1512_06025_amd/build.py)")
+        raise ImportError("libbbdg.so is not built (run python paper_1512_06025_amd/build.py)")
     lib = ctypes.CDLL(LIB_PATH)
     for name, (res, args) in SIGNATURES.items():
         fn = getattr(lib, name)
