@@ -107,10 +107,15 @@ template <int N, typename T, int TW>
 struct Team {
   using S = Shape<N, T>;
   static constexpr int TPE = 64 * TW;
-  static constexpr int E = TPE / S::Np > 1 ? TPE / S::Np : 1;    // elements per group
-  static constexpr int NPL = (E * S::Np + TPE - 1) / TPE;         // nodes per thread
-  static constexpr int SF = item_stride(S::Nfp, E * 4, TPE);      // face-item position stride
-  static constexpr int NFI = (E * 4 * SF + TPE - 1) / TPE;        // face items per thread
+  // FP32 one-wave groups at N = 5 hold two elements interleaved: lane n takes
+  // node n (and face item n) of both, so every index table of a node or a
+  // face item is read and decoded once for the two elements.
+  static constexpr bool IL = sizeof(T) == 4 && N == 5 && TW == 1;
+  static constexpr int E = IL ? 2 : (TPE / S::Np > 1 ? TPE / S::Np : 1);  // elements per group
+  static constexpr int NPL = IL ? E : (E * S::Np + TPE - 1) / TPE;         // nodes per thread
+  static constexpr int SF = IL ? item_stride(S::Nfp, 4, 64) : item_stride(S::Nfp, E * 4, TPE);  // face-item stride
+  static constexpr int NFE = IL ? (4 * SF + 63) / 64 : 1;                  // face-item passes per element
+  static constexpr int NFI = IL ? E * NFE : (E * 4 * SF + TPE - 1) / TPE;  // face items per thread
   static constexpr int NHE = (E * 4 + TPE - 1) / TPE;
 };
 
@@ -308,13 +313,15 @@ void bb_stage_kernel(StageArgs<T> A) {
   static_assert(WPB % TW == 0 && (TW == 1 || TW == WPB), "a team is one wave or the whole workgroup");
   using M = Team<N, T, TW>;
   constexpr int TEAMS = WPB / TW, TPE = M::TPE;
-  constexpr int Np = S::Np, Nfp = S::Nfp, E = M::E, NPL = M::NPL, NFI = M::NFI;
+  constexpr int Np = S::Np, Nfp = S::Nfp, E = M::E, NPL = M::NPL;
   constexpr int FB = TW > 1 ? S::FBT : S::FB1, GEO = S::GEO;
   constexpr bool kUpdate = (MODE == kStage || kBatch);
   // FP32 up to N = 6 keeps (h_i, p) pairs per node (one 8-byte read per
   // direction, 40-byte node stride free of bank conflicts); otherwise the
   // five values are stored field by field (less LDS)
-  constexpr bool kPairSq = sizeof(T) == 4 && N <= 6;
+  // (interleaved groups take the field-by-field layout: the pairs' LDS would
+  // cost a workgroup per CU)
+  constexpr bool kPairSq = sizeof(T) == 4 && N <= 6 && !M::IL;
   constexpr int SQW = kPairSq ? 10 : 5;  // words per node of sq
   constexpr bool kVol = (MODE != kRhsSurface);
   constexpr bool kSurf = (MODE != kRhsVolume);
@@ -424,6 +431,35 @@ void bb_stage_kernel(StageArgs<T> A) {
       for (int i = 0; i < 4; ++i) sq[w][el][1 + i][n] = hv[i];
     }
   };
+  // Node r of a thread: element el of the group and node n (false: none).
+  auto node_of = [&](int ln, int r, int& el, int& n) -> bool {
+    if constexpr (M::IL) {
+      el = r;
+      n = ln;
+      return ln < Np;
+    } else {
+      const int v = ln + TPE * r;
+      el = E == 1 ? 0 : v / Np;
+      n = v - el * Np;
+      return v < E * Np;
+    }
+  };
+  // Face item r of a thread: position gg, face f, element el (false: none).
+  auto face_item = [&](int ln, int r, unsigned& gg, int& f, unsigned& el) -> bool {
+    if constexpr (M::IL) {
+      const unsigned v = (unsigned)ln + 64u * (unsigned)(r % M::NFE);
+      gg = v % M::SF;
+      f = (int)(v / M::SF);
+      el = (unsigned)(r / M::NFE);
+      return f < 4 && gg < (unsigned)Nfp;
+    } else {
+      const unsigned v = (unsigned)ln + TPE * r;
+      gg = v % M::SF;
+      f = (int)((v / M::SF) % 4);
+      el = v / (4 * M::SF);
+      return el < (unsigned)E && gg < (unsigned)Nfp;
+    }
+  };
   const int64_t K = A.K;
   const int64_t KNp = K * Np;
   const int64_t G = (K + E - 1) / E;  // element groups per shot
@@ -496,10 +532,8 @@ void bb_stage_kernel(StageArgs<T> A) {
     uint32_t noff[NPL];  // e 4 Np + n of the thread's nodes (field p)
 #pragma unroll
     for (int r = 0; r < NPL; ++r) {
-      const int v = lane + TPE * r;
-      const int el = E == 1 ? 0 : v / Np;
-      const int n = v - el * Np;
-      const bool ok = (v < E * Np) && (e0 + el < K);
+      int el, n;
+      const bool ok = node_of(lane, r, el, n) && (e0 + el < K);
       noff[r] = ok ? (uint32_t)((e0 + el) * 4 * Np + n) : 0u;
       const T* qp = qin_s + noff[r];
 #pragma unroll
@@ -513,16 +547,15 @@ void bb_stage_kernel(StageArgs<T> A) {
         for (int f = 0; f < 4; ++f) rv[r][f] = 0;
       }
     }
-    T tr[NFI][4];
+    T tr[M::NFI][4];
     if constexpr (kSurf) {
 #pragma unroll
-      for (int r = 0; r < NFI; ++r) {
-        const unsigned v = lane + TPE * r;
-        const unsigned gg = v % M::SF;
-        const unsigned f = (v / M::SF) % 4;
-        const unsigned el = v / (4 * M::SF);
+      for (int r = 0; r < M::NFI; ++r) {
+        unsigned gg, el;
+        int f;
+        const bool item = face_item(lane, r, gg, f, el);
         uint32_t off = 0;
-        if (el < (unsigned)E && gg < (unsigned)Nfp && e0 + el < K) {
+        if (item && e0 + el < K) {
           const int nb = she[w][el * 4 + f];
           const int info = shf[w][el * 4 + f];
           if (nb >= 0) off = (uint32_t)nb * (4 * Np) + t_nbr[((info & 3) * 6 + (info >> 2)) * Nfp + gg];
@@ -570,10 +603,8 @@ void bb_stage_kernel(StageArgs<T> A) {
     T hreg[NPL][4];  // h_i of the own nodes
 #pragma unroll
     for (int r = 0; r < NPL; ++r) {
-      const int v = lane + TPE * r;
-      if (v < E * Np) {
-        const int el = E == 1 ? 0 : v / Np;
-        const int n = v - el * Np;
+      int el, n;
+      if (node_of(lane, r, el, n)) {
         T* hv = hreg[r];
         if constexpr (H::kTG) {
           // h_i from grad(lambda_i) of the derived geometry (in LDS since the last sync)
@@ -604,10 +635,8 @@ void bb_stage_kernel(StageArgs<T> A) {
     if constexpr (kVol) {
 #pragma unroll
       for (int r = 0; r < NPL; ++r) {
-        const int v = lane + TPE * r;
-        if (v >= E * Np) continue;
-        const int el = E == 1 ? 0 : v / Np;
-        const int n = v - el * Np;
+        int el, n;
+        if (!node_of(lane, r, el, n)) continue;
         const uint32_t ap = t_alpha[n];
         const T av[4] = {(T)(ap & 255), (T)((ap >> 8) & 255), (T)((ap >> 16) & 255), (T)(ap >> 24)};
         int nb[12];
@@ -658,12 +687,10 @@ void bb_stage_kernel(StageArgs<T> A) {
       for (int fb0 = 0; fb0 < 4; fb0 += FB) {
         // flux on the face nodes of faces fb0 .. fb0+FB-1
 #pragma unroll
-        for (int r = 0; r < NFI; ++r) {
-          const unsigned v = lane + TPE * r;
-          const unsigned gg = v % M::SF;
-          const int f = (v / M::SF) % 4;
-          const unsigned el = v / (4 * M::SF);
-          if (el >= (unsigned)E || gg >= (unsigned)Nfp || f < fb0 || f >= fb0 + FB) continue;
+        for (int r = 0; r < M::NFI; ++r) {
+          unsigned gg, el;
+          int f;
+          if (!face_item(lane, r, gg, f, el) || f < fb0 || f >= fb0 + FB) continue;
           T sp = 0, su = 0;
           if (e0 + el < K) {
             const int n = t_fnode[f * Nfp + gg];
@@ -696,24 +723,33 @@ void bb_stage_kernel(StageArgs<T> A) {
         team_sync<TW>();
 
         // w_0 = L_0 s, one row per (face, position) item, position fastest
-        constexpr unsigned SL0 = item_stride(Nfp, E * FB, TPE);
-        for (unsigned v = lane; v < E * FB * SL0; v += TPE) {
+        // (interleaved groups: an item's tables serve the LREP elements)
+        constexpr unsigned LGR = M::IL ? FB : E * FB;  // face vectors per item space
+        constexpr unsigned LREP = M::IL ? E : 1;       // elements sharing an item
+        constexpr unsigned SL0 = item_stride(Nfp, LGR, TPE);
+        for (unsigned v = lane; v < LGR * SL0; v += TPE) {
           const unsigned gg = v % SL0;
-          const unsigned rest = v / SL0;  // = el * FB + face in the batch
+          const unsigned g0 = v / SL0;  // = el * FB + face in the batch (face in the batch if interleaved)
           if (gg >= Nfp) continue;
-          const Pair<T>* sv = &sfl[w][0][0][0] + rest * Nfp;
           const uint2 pp = *reinterpret_cast<const uint2*>(t_l0p[gg]);
           const unsigned pos[7] = {gg, (pp.x >> 8) & 255, (pp.x >> 16) & 255, pp.x >> 24,
                                    pp.y & 255, (pp.y >> 8) & 255, (pp.y >> 16) & 255};
-          T ap = 0, au = 0;
+          T c[7];
 #pragma unroll
-          for (int q = 0; q < 7; ++q) {
-            const T c = t_l0c[q][gg];
-            const Pair<T> x = sv[pos[q]];
-            ap += c * x.p;
-            au += c * x.u;
+          for (int q = 0; q < 7; ++q) c[q] = t_l0c[q][gg];
+#pragma unroll
+          for (unsigned e2 = 0; e2 < LREP; ++e2) {
+            const unsigned rest = g0 + e2 * FB;
+            const Pair<T>* sv = &sfl[w][0][0][0] + rest * Nfp;
+            T ap = 0, au = 0;
+#pragma unroll
+            for (int q = 0; q < 7; ++q) {
+              const Pair<T> x = sv[pos[q]];
+              ap += c[q] * x.p;
+              au += c[q] * x.u;
+            }
+            (&slev[w][0][0][0])[rest * Np + gg] = Pair<T>{ap, au};
           }
-          (&slev[w][0][0][0])[rest * Np + gg] = Pair<T>{ap, au};
         }
         team_sync<TW>();
 
@@ -722,18 +758,21 @@ void bb_stage_kernel(StageArgs<T> A) {
         for (int j = 1; j <= N; ++j) {
           const int out0 = level_off(j, N);
           const int Tm = tri_of(N - j);
-          const unsigned SM = item_stride(Tm, E * FB, TPE);
-          for (unsigned v = lane; v < E * FB * SM; v += TPE) {
+          const unsigned SM = item_stride(Tm, LGR, TPE);
+          for (unsigned v = lane; v < LGR * SM; v += TPE) {
             const unsigned s = v % SM;
-            const unsigned rest = v / SM;  // = el * FB + face in the batch
+            const unsigned g0 = v / SM;  // = el * FB + face in the batch (face in the batch if interleaved)
             if (s >= (unsigned)Tm) continue;
             const unsigned nn = out0 + s;
-            Pair<T>* wv = &slev[w][0][0][0] + rest * Np;
             const uint32_t ip = t_lvp[nn];
             const unsigned i0 = ip & 0xffff, i2 = ip >> 16;
             const T c0 = t_lvc[0][nn], c1 = t_lvc[1][nn], c2 = t_lvc[2][nn];
-            const Pair<T> x0 = wv[i0], x1 = wv[i0 + 1], x2 = wv[i2];
-            wv[nn] = Pair<T>{c0 * x0.p + c1 * x1.p + c2 * x2.p, c0 * x0.u + c1 * x1.u + c2 * x2.u};
+#pragma unroll
+            for (unsigned e2 = 0; e2 < LREP; ++e2) {
+              Pair<T>* wv = &slev[w][0][0][0] + (g0 + e2 * FB) * Np;
+              const Pair<T> x0 = wv[i0], x1 = wv[i0 + 1], x2 = wv[i2];
+              wv[nn] = Pair<T>{c0 * x0.p + c1 * x1.p + c2 * x2.p, c0 * x0.u + c1 * x1.u + c2 * x2.u};
+            }
           }
           team_sync<TW>();
         }
@@ -741,10 +780,8 @@ void bb_stage_kernel(StageArgs<T> A) {
         // gather the lifted values of this batch into the nodes
 #pragma unroll
         for (int r = 0; r < NPL; ++r) {
-          const int v = lane + TPE * r;
-          if (v >= E * Np) continue;
-          const int el = E == 1 ? 0 : v / Np;
-          const int n = v - el * Np;
+          int el, n;
+          if (!node_of(lane, r, el, n)) continue;
           const uint32_t ap = t_alpha[n];
 #pragma unroll
           for (int fl = 0; fl < FB; ++fl) {
@@ -771,22 +808,20 @@ void bb_stage_kernel(StageArgs<T> A) {
       const int32_t se = A.src_elem ? A.src_elem[shot] : -1;
 #pragma unroll
       for (int r = 0; r < NPL; ++r) {
-        const int v = lane + TPE * r;
-        const int el = E == 1 ? 0 : v / Np;
-        if (v < E * Np && e0 + el == se) rhs[r][0] += amp * A.src_coef[shot * Np + (v - el * Np)];
+        int el, n;
+        if (node_of(lane, r, el, n) && e0 + el == se) rhs[r][0] += amp * A.src_coef[shot * Np + n];
       }
     }
 
     // ---- update / store -------------------------------------------------------------
 #pragma unroll
     for (int r = 0; r < NPL; ++r) {
-      const int v = lane + TPE * r;
-      const int el = E == 1 ? 0 : v / Np;
-      if (v >= E * Np || e0 + el >= K) continue;
+      int el, n;
+      if (!node_of(lane, r, el, n) || e0 + el >= K) continue;
       T* const rp = res_s + noff[r];
       T* const op = qout_s + noff[r];
       if constexpr (kUpdate) {
-        if constexpr (kRecord) A.rec_p[(stage * A.shots + shot) * KNp + (e0 + el) * Np + (v - el * Np)] = rhs[r][0];
+        if constexpr (kRecord) A.rec_p[(stage * A.shots + shot) * KNp + (e0 + el) * Np + n] = rhs[r][0];
         const T dt = kBatch ? (T)A.dtd : A.dt;
 #pragma unroll
         for (int f = 0; f < 4; ++f) {
