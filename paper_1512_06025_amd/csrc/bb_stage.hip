@@ -722,59 +722,104 @@ void bb_stage_kernel(StageArgs<T> A) {
         }
         team_sync<TW>();
 
-        // w_0 = L_0 s, one row per (face, position) item, position fastest
-        // (interleaved groups: an item's tables serve the LREP elements)
-        constexpr unsigned LGR = M::IL ? FB : E * FB;  // face vectors per item space
-        constexpr unsigned LREP = M::IL ? E : 1;       // elements sharing an item
-        constexpr unsigned SL0 = item_stride(Nfp, LGR, TPE);
-        for (unsigned v = lane; v < LGR * SL0; v += TPE) {
-          const unsigned gg = v % SL0;
-          const unsigned g0 = v / SL0;  // = el * FB + face in the batch (face in the batch if interleaved)
-          if (gg >= Nfp) continue;
-          const uint2 pp = *reinterpret_cast<const uint2*>(t_l0p[gg]);
-          const unsigned pos[7] = {gg, (pp.x >> 8) & 255, (pp.x >> 16) & 255, pp.x >> 24,
-                                   pp.y & 255, (pp.y >> 8) & 255, (pp.y >> 16) & 255};
-          T c[7];
-#pragma unroll
-          for (int q = 0; q < 7; ++q) c[q] = t_l0c[q][gg];
-#pragma unroll
-          for (unsigned e2 = 0; e2 < LREP; ++e2) {
-            const unsigned rest = g0 + e2 * FB;
-            const Pair<T>* sv = &sfl[w][0][0][0] + rest * Nfp;
-            T ap = 0, au = 0;
-#pragma unroll
-            for (int q = 0; q < 7; ++q) {
-              const Pair<T> x = sv[pos[q]];
-              ap += c[q] * x.p;
-              au += c[q] * x.u;
-            }
-            (&slev[w][0][0][0])[rest * Np + gg] = Pair<T>{ap, au};
-          }
-        }
-        team_sync<TW>();
-
-        // one-degree reductions, level j = 1..N, one row per (face, position) item
-#pragma unroll
-        for (int j = 1; j <= N; ++j) {
-          const int out0 = level_off(j, N);
-          const int Tm = tri_of(N - j);
-          const unsigned SM = item_stride(Tm, LGR, TPE);
-          for (unsigned v = lane; v < LGR * SM; v += TPE) {
-            const unsigned s = v % SM;
-            const unsigned g0 = v / SM;  // = el * FB + face in the batch (face in the batch if interleaved)
-            if (s >= (unsigned)Tm) continue;
-            const unsigned nn = out0 + s;
-            const uint32_t ip = t_lvp[nn];
-            const unsigned i0 = ip & 0xffff, i2 = ip >> 16;
-            const T c0 = t_lvc[0][nn], c1 = t_lvc[1][nn], c2 = t_lvc[2][nn];
-#pragma unroll
+        if constexpr (M::IL) {
+          // w_0 = L_0 s, one row per (face, position) item, position fastest
+          // (interleaved groups: an item's tables serve the LREP elements)
+          constexpr unsigned LGR = M::IL ? FB : E * FB;  // face vectors per item space
+          constexpr unsigned LREP = M::IL ? E : 1;       // elements sharing an item
+          constexpr unsigned SL0 = item_stride(Nfp, LGR, TPE);
+          for (unsigned v = lane; v < LGR * SL0; v += TPE) {
+            const unsigned gg = v % SL0;
+            const unsigned g0 = v / SL0;  // = el * FB + face in the batch (face in the batch if interleaved)
+            if (gg >= Nfp) continue;
+            const uint2 pp = *reinterpret_cast<const uint2*>(t_l0p[gg]);
+            const unsigned pos[7] = {gg, (pp.x >> 8) & 255, (pp.x >> 16) & 255, pp.x >> 24,
+                                     pp.y & 255, (pp.y >> 8) & 255, (pp.y >> 16) & 255};
+            T c[7];
+  #pragma unroll
+            for (int q = 0; q < 7; ++q) c[q] = t_l0c[q][gg];
+  #pragma unroll
             for (unsigned e2 = 0; e2 < LREP; ++e2) {
-              Pair<T>* wv = &slev[w][0][0][0] + (g0 + e2 * FB) * Np;
-              const Pair<T> x0 = wv[i0], x1 = wv[i0 + 1], x2 = wv[i2];
-              wv[nn] = Pair<T>{c0 * x0.p + c1 * x1.p + c2 * x2.p, c0 * x0.u + c1 * x1.u + c2 * x2.u};
+              const unsigned rest = g0 + e2 * FB;
+              const Pair<T>* sv = &sfl[w][0][0][0] + rest * Nfp;
+              T ap = 0, au = 0;
+  #pragma unroll
+              for (int q = 0; q < 7; ++q) {
+                const Pair<T> x = sv[pos[q]];
+                ap += c[q] * x.p;
+                au += c[q] * x.u;
+              }
+              (&slev[w][0][0][0])[rest * Np + gg] = Pair<T>{ap, au};
             }
           }
           team_sync<TW>();
+
+          // one-degree reductions, level j = 1..N, one row per (face, position) item
+  #pragma unroll
+          for (int j = 1; j <= N; ++j) {
+            const int out0 = level_off(j, N);
+            const int Tm = tri_of(N - j);
+            const unsigned SM = item_stride(Tm, LGR, TPE);
+            for (unsigned v = lane; v < LGR * SM; v += TPE) {
+              const unsigned s = v % SM;
+              const unsigned g0 = v / SM;  // = el * FB + face in the batch (face in the batch if interleaved)
+              if (s >= (unsigned)Tm) continue;
+              const unsigned nn = out0 + s;
+              const uint32_t ip = t_lvp[nn];
+              const unsigned i0 = ip & 0xffff, i2 = ip >> 16;
+              const T c0 = t_lvc[0][nn], c1 = t_lvc[1][nn], c2 = t_lvc[2][nn];
+  #pragma unroll
+              for (unsigned e2 = 0; e2 < LREP; ++e2) {
+                Pair<T>* wv = &slev[w][0][0][0] + (g0 + e2 * FB) * Np;
+                const Pair<T> x0 = wv[i0], x1 = wv[i0 + 1], x2 = wv[i2];
+                wv[nn] = Pair<T>{c0 * x0.p + c1 * x1.p + c2 * x2.p, c0 * x0.u + c1 * x1.u + c2 * x2.u};
+              }
+            }
+            team_sync<TW>();
+          }
+        } else {
+          // w_0 = L_0 s, one row per (face, position) item, position fastest
+          constexpr unsigned SL0 = item_stride(Nfp, E * FB, TPE);
+          for (unsigned v = lane; v < E * FB * SL0; v += TPE) {
+            const unsigned gg = v % SL0;
+            const unsigned rest = v / SL0;  // = el * FB + face in the batch
+            if (gg >= Nfp) continue;
+            const Pair<T>* sv = &sfl[w][0][0][0] + rest * Nfp;
+            const uint2 pp = *reinterpret_cast<const uint2*>(t_l0p[gg]);
+            const unsigned pos[7] = {gg, (pp.x >> 8) & 255, (pp.x >> 16) & 255, pp.x >> 24,
+                                     pp.y & 255, (pp.y >> 8) & 255, (pp.y >> 16) & 255};
+            T ap = 0, au = 0;
+  #pragma unroll
+            for (int q = 0; q < 7; ++q) {
+              const T c = t_l0c[q][gg];
+              const Pair<T> x = sv[pos[q]];
+              ap += c * x.p;
+              au += c * x.u;
+            }
+            (&slev[w][0][0][0])[rest * Np + gg] = Pair<T>{ap, au};
+          }
+          team_sync<TW>();
+
+          // one-degree reductions, level j = 1..N, one row per (face, position) item
+  #pragma unroll
+          for (int j = 1; j <= N; ++j) {
+            const int out0 = level_off(j, N);
+            const int Tm = tri_of(N - j);
+            const unsigned SM = item_stride(Tm, E * FB, TPE);
+            for (unsigned v = lane; v < E * FB * SM; v += TPE) {
+              const unsigned s = v % SM;
+              const unsigned rest = v / SM;  // = el * FB + face in the batch
+              if (s >= (unsigned)Tm) continue;
+              const unsigned nn = out0 + s;
+              Pair<T>* wv = &slev[w][0][0][0] + rest * Np;
+              const uint32_t ip = t_lvp[nn];
+              const unsigned i0 = ip & 0xffff, i2 = ip >> 16;
+              const T c0 = t_lvc[0][nn], c1 = t_lvc[1][nn], c2 = t_lvc[2][nn];
+              const Pair<T> x0 = wv[i0], x1 = wv[i0 + 1], x2 = wv[i2];
+              wv[nn] = Pair<T>{c0 * x0.p + c1 * x1.p + c2 * x2.p, c0 * x0.u + c1 * x1.u + c2 * x2.u};
+            }
+            team_sync<TW>();
+          }
         }
 
         // gather the lifted values of this batch into the nodes
