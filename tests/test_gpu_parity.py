@@ -258,3 +258,29 @@ def test_nodal_ept_stage_parity(N, dtype):
     err = _rel(_host(xd), want)
     assert err < NODAL_TOL[dtype], (N, dtype, err)
     s.close()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("N", [3, 5])
+def test_set_wavespeed_then_step(N, dtype):
+    """bbdg_set_wavespeed replaces the wavespeed of an existing handle (the
+    upwind weights of the header and the per-element geometry the stage
+    kernels load, precomputed on the host): one LSRK4 step after the switch
+    matches the oracle built with the new wavespeed, on every coefficient."""
+    from paper_1512_06025_amd import _lib
+    P, mesh, c_old, _ = _setup(3, N, c=(1.0, 3.0), drop_last=7)
+    c_new = np.ascontiguousarray(workload.wavespeed(c_old.shape[0], 0.5, 2.0, seed=123))
+    assert np.abs(c_new - c_old).max() > 0.1
+    VX, EToV = workload.kuhn_cube_mesh(3, 0.1, drop_last=7)
+    prob = dg.Problem(VX, EToV, N, c_new)
+    q = workload.random_coeffs(prob.K, prob.Np, seed=80 + N)
+    if dtype == "f32":
+        q = q.astype(np.float32).astype(np.float64)
+    s = P.Solver(N, mesh, c_old, dtype=dtype)
+    _lib.check(_lib.load().bbdg_set_wavespeed(s._h, c_new.ctypes.data), "bbdg_set_wavespeed")
+    qd = _to_dev(q, dtype)
+    dt = 0.4 / (3.0 * 3 * (N + 1) ** 2)
+    s.run(qd, dt, 1)
+    err = _rel(_host(qd), prob.lsrk4(q, dt, 1))
+    assert err < TOL[dtype], (N, dtype, err)
+    s.close()
