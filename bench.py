@@ -246,7 +246,10 @@ def time_batched(P, torch, workload, steps):
 def time_gradient(P, torch, workload, steps):
     """Misfit and its gradient in m = c^2: 8 shots on 24,576 tets, N = 5,
     FP32 states (FP64 gradient sums), observations from the FP64 forward run
-    at a blob model, gradient at m = 1, checkpoints every 50 steps."""
+    at a blob model, gradient at m = 1, checkpoints every 50 steps, stage
+    records of as many segments as the free device memory holds.  The ratio
+    is (J + dJ/dm) over a plain forward run of the same shots (traces only,
+    no checkpoints or records)."""
     cfg, VX, EToV, _ = workload.build_preset("c5")
     N, K, S, dt = cfg["N"], cfg["K"], cfg["shots"], cfg["dt"]
     mesh = P.mesh_geometry(VX, EToV)
@@ -257,26 +260,37 @@ def time_gradient(P, torch, workload, steps):
                               dtype="f64", wpb=4)
     d_obs = obs_run.run(obs_run.empty_state(), dt, steps).clone()
     obs_run.close()
+    del obs_run
+    gc.collect()
+    torch.cuda.empty_cache()
     mf = P.Misfit(N, mesh, np.ones(K), S, src, rec, d_obs, dt, steps, f0=cfg["f0"], ts=cfg["ts"],
-                  ckpt_every=cfg["ckpt_every"], dtype="f32")
+                  ckpt_every=cfg["ckpt_every"], dtype="f32", rec_segments="max")
     mf.evaluate()
     mf.gradient()  # warm-up
+    q_plain = mf.batched.empty_state()
+    mf.batched.run(q_plain, dt, steps)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
     ev[0].record(stream)
-    J = mf.evaluate()
+    mf.batched.run(q_plain.zero_(), dt, steps)
     ev[1].record(stream)
-    g = mf.gradient()
+    torch.cuda.synchronize()
     ev[2].record(stream)
+    J = mf.evaluate()
+    ev[3].record(stream)
+    g = mf.gradient()
+    ev[4].record(stream)
     torch.cuda.synchronize()
     mf.check()
-    t_fwd, t_adj = ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2])
+    t_plain, t_fwd, t_adj = ev[0].elapsed_time(ev[1]), ev[2].elapsed_time(ev[3]), ev[3].elapsed_time(ev[4])
     finite = bool(torch.isfinite(g).all().item())
     g = g.clone()
+    M = mf.rec_segments
     mf.close()
-    del mf
+    del mf, q_plain
     gc.collect()
+    torch.cuda.empty_cache()
     # the same gradient with FP64 states (untimed) for the FP32 error
     m64 = P.Misfit(N, mesh, np.ones(K), S, src, rec, d_obs, dt, steps, f0=cfg["f0"], ts=cfg["ts"],
                    ckpt_every=cfg["ckpt_every"], dtype="f64")
@@ -287,10 +301,10 @@ def time_gradient(P, torch, workload, steps):
     del m64
     gc.collect()
     out = {"workload": "misfit gradient dJ/dm, %d shots (Ricker f0=%g on z=0.9), 64 receivers, %d^3x6 = %d tets, "
-                       "N=%d, FP32 states / FP64 sums, %d steps, checkpoints every %d" % (
-                           S, cfg["f0"], cfg["n"], K, N, steps, cfg["ckpt_every"]),
-           "J": float(J.item()), "forward_ms": t_fwd, "reverse_ms": t_adj,
-           "grad_over_forward": (t_fwd + t_adj) / t_fwd, "reverse_over_forward": t_adj / t_fwd,
+                       "N=%d, FP32 states / FP64 sums, %d steps, checkpoints every %d, records of %d segments" % (
+                           S, cfg["f0"], cfg["n"], K, N, steps, cfg["ckpt_every"], M),
+           "J": float(J.item()), "plain_forward_ms": t_plain, "forward_ms": t_fwd, "reverse_ms": t_adj,
+           "rec_segments": M, "grad_over_forward": (t_fwd + t_adj) / t_plain, "reverse_over_forward": t_adj / t_plain,
            "finite": finite, "J_rel_error_vs_fp64": abs(float(J.item()) - J64) / abs(J64),
            "grad_rel_l2_error_vs_fp64": float(torch.linalg.norm(g - g64) / torch.linalg.norm(g64))}
     return out

@@ -327,9 +327,13 @@ int bbdg_batched_occupancy(const bbdg_solver* s, int wpb, int record, int32_t* o
  * weights tau_p = 2/(c- + c+), tau_u = (c- + c+)/2 and of the source vector
  * on m.  States use the solver's element type; gradient sums are FP64.
  * The forward states are kept at checkpoints every ckpt_every steps (0 = only
- * the initial state); the forward run records the stages of its last
- * segment, and every other segment is recomputed once, recording its
- * stages, during the reverse sweep. */
+ * the initial state).  The work space holds the stage records of
+ * rec_segments segments (>= 1; values above the segment count hold all of
+ * them): the forward run records its last rec_segments segments, and every
+ * other segment is recomputed once from its checkpoint, recording its stages,
+ * during the reverse sweep.  A record slot takes 5 * ckpt_every * shots * K *
+ * (Np + 8 Nfp) elements, so the caller trades device memory for recomputed
+ * steps. */
 
 /* Replaces the wavespeed (host, K doubles, c > 0) of a solver; the mesh is
  * unchanged.  Source vectors scale with kappa of their element: recompute
@@ -337,18 +341,20 @@ int bbdg_batched_occupancy(const bbdg_solver* s, int wpb, int record, int32_t* o
 int bbdg_set_wavespeed(bbdg_solver* s, const double* c);
 
 /* Bytes of device work space for bbdg_misfit / bbdg_misfit_gradient with
- * these sizes (0 for invalid sizes). */
-size_t bbdg_misfit_work_bytes(const bbdg_solver* s, int64_t shots, int R, int64_t steps, int64_t ckpt_every);
+ * these sizes (0 for invalid sizes, rec_segments < 1 included). */
+size_t bbdg_misfit_work_bytes(const bbdg_solver* s, int64_t shots, int R, int64_t steps, int64_t ckpt_every,
+                              int64_t rec_segments);
 
 /* Runs the batched forward problem from q0 (device (shots, K, 4, Np), or NULL
  * for zero initial states), keeps checkpoints and traces in work (device,
  * >= bbdg_misfit_work_bytes, 256-byte aligned) and writes J (device, one
  * double).  Arguments as bbdg_run_batched; obs: device (steps, shots, R) of
- * the element type; R >= 1, steps >= 1. */
+ * the element type; R >= 1, steps >= 1, rec_segments >= 1 (else
+ * BBDG_E_ARG) and the same as for bbdg_misfit_work_bytes. */
 int bbdg_misfit(bbdg_solver* s, int64_t shots, const void* q0, const int32_t* src_elem,
                 const void* src_coef, double f0, double ts, int R, const int32_t* rec_elem,
                 const void* rec_coef, const void* obs, double t0, double dt, int64_t steps,
-                int64_t ckpt_every, double* J, void* work, void* stream);
+                int64_t ckpt_every, int64_t rec_segments, double* J, void* work, void* stream);
 
 /* Gradient dJ/dm (device, K doubles) of the misfit of the last bbdg_misfit
  * call on the same work space, with the same arguments (its checkpoints and
@@ -356,7 +362,8 @@ int bbdg_misfit(bbdg_solver* s, int64_t shots, const void* q0, const int32_t* sr
 int bbdg_misfit_gradient(bbdg_solver* s, int64_t shots, const void* q0, const int32_t* src_elem,
                          const void* src_coef, double f0, double ts, int R, const int32_t* rec_elem,
                          const void* rec_coef, const void* obs, double t0, double dt, int64_t steps,
-                         int64_t ckpt_every, double* grad, void* work, void* stream);
+                         int64_t ckpt_every, int64_t rec_segments, double* grad, void* work,
+                         void* stream);
 
 /* Measurement aid, not part of the method: copies `bytes` (a multiple of 16,
  * both pointers 16-byte aligned, no overlap) from device buffer src to dst

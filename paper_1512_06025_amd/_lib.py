@@ -68,14 +68,16 @@ SIGNATURES = {
     "bbdg_tune_batched": (_c.c_int, [_c.c_void_p, _c.c_int64, _c.c_void_p, _c.POINTER(_c.c_int),
                                      _c.c_void_p]),
     "bbdg_set_wavespeed": (_c.c_int, [_c.c_void_p, _c.c_void_p]),
-    "bbdg_misfit_work_bytes": (_c.c_size_t, [_c.c_void_p, _c.c_int64, _c.c_int, _c.c_int64, _c.c_int64]),
+    "bbdg_misfit_work_bytes": (_c.c_size_t, [_c.c_void_p, _c.c_int64, _c.c_int, _c.c_int64, _c.c_int64,
+                                             _c.c_int64]),
     "bbdg_misfit": (_c.c_int, [_c.c_void_p, _c.c_int64, _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_double,
                                _c.c_double, _c.c_int, _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_double,
-                               _c.c_double, _c.c_int64, _c.c_int64, _c.c_void_p, _c.c_void_p, _c.c_void_p]),
+                               _c.c_double, _c.c_int64, _c.c_int64, _c.c_int64, _c.c_void_p, _c.c_void_p,
+                               _c.c_void_p]),
     "bbdg_misfit_gradient": (_c.c_int, [_c.c_void_p, _c.c_int64, _c.c_void_p, _c.c_void_p, _c.c_void_p,
                                         _c.c_double, _c.c_double, _c.c_int, _c.c_void_p, _c.c_void_p,
                                         _c.c_void_p, _c.c_double, _c.c_double, _c.c_int64, _c.c_int64,
-                                        _c.c_void_p, _c.c_void_p, _c.c_void_p]),
+                                        _c.c_int64, _c.c_void_p, _c.c_void_p, _c.c_void_p]),
     "bbdg_last_hip_error": (_c.c_int, []),
     "bbdg_copy_probe": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_size_t, _c.c_void_p]),
     "bbdg_destroy": (_c.c_int, [_c.c_void_p]),

@@ -47,8 +47,8 @@ struct bbdg_solver {
   std::vector<int32_t> h_etoe;       // K x 4
   int64_t tuned_shots = 0;           // shot count bbdg_tune_batched ran for
   int tuned_wpb = 0;                 // and the waves per workgroup it chose
-  const void* rec_work = nullptr;    // misfit work space whose stage records hold
-  int64_t rec_seg = -1;              // this segment (-1: none)
+  const void* rec_work = nullptr;    // misfit work space whose record slots hold
+  std::vector<int64_t> rec_seg;      // these segments, one per slot (-1: none)
   int store_policy = BBDG_STORES_AUTO;  // output stores of the FP64 time-stepping stage
 };
 
@@ -663,18 +663,22 @@ int misfit_wpb(const bbdg_solver* s, int64_t shots) {
 }
 
 // Work-space layout of the misfit and its gradient (offsets in bytes, each
-// part 256-byte aligned).
+// part 256-byte aligned).  The stage records come in M slots of one segment
+// each; segment g always uses slot g mod M.
 struct GradLayout {
-  int64_t C = 0, nseg = 0;
+  int64_t C = 0, nseg = 0, M = 0;
   size_t state = 0, fwork = 0, ckpt = 0, traces = 0, rec_p = 0, rec_j = 0, rb = 0, qb = 0, z = 0, gk = 0, gt = 0,
          amp = 0;
+  size_t slot_p = 0, slot_j = 0;  // elements per slot of rec_p and rec_j
   size_t total = 0;
 };
 
-GradLayout grad_layout(const bbdg_solver* s, int64_t shots, int R, int64_t steps, int64_t ckpt_every) {
+GradLayout grad_layout(const bbdg_solver* s, int64_t shots, int R, int64_t steps, int64_t ckpt_every,
+                       int64_t rec_segments) {
   GradLayout g;
   g.C = (ckpt_every <= 0 || ckpt_every > steps) ? steps : ckpt_every;
   g.nseg = g.C > 0 ? (steps + g.C - 1) / g.C : 0;
+  g.M = std::max<int64_t>(1, std::min(rec_segments, g.nseg));
   const size_t w = elem_size(s->dtype);
   const size_t Np = (size_t)np_of(s->N), Nfp = (size_t)nfp_of(s->N), K = (size_t)s->K, S = (size_t)shots;
   const size_t st = S * 4 * K * Np * w;
@@ -688,8 +692,10 @@ GradLayout grad_layout(const bbdg_solver* s, int64_t shots, int R, int64_t steps
   g.fwork = take(2 * st);
   g.ckpt = take((size_t)g.nseg * st);
   g.traces = take((size_t)steps * S * (size_t)R * w);
-  g.rec_p = take(5 * (size_t)g.C * S * K * Np * w);
-  g.rec_j = take(5 * (size_t)g.C * S * K * 8 * Nfp * w);
+  g.slot_p = 5 * (size_t)g.C * S * K * Np;
+  g.slot_j = 5 * (size_t)g.C * S * K * 8 * Nfp;
+  g.rec_p = take((size_t)g.M * g.slot_p * w);
+  g.rec_j = take((size_t)g.M * g.slot_j * w);
   g.rb = take(st);
   g.qb = take(st);
   g.z = take(2 * S * K * 8 * Nfp * w);
@@ -705,9 +711,9 @@ GradLayout grad_layout(const bbdg_solver* s, int64_t shots, int R, int64_t steps
 template <typename T>
 int misfit_typed(bbdg_solver* s, int64_t shots, const T* q0, const int32_t* src_elem, const T* src_coef, double f0,
                  double ts, int R, const int32_t* rec_elem, const T* rec_coef, const T* obs, double t0, double dt,
-                 int64_t steps, int64_t ckpt_every, double* J, double* grad, bool forward, char* work,
-                 hipStream_t st) {
-  const GradLayout L = grad_layout(s, shots, R, steps, ckpt_every);
+                 int64_t steps, int64_t ckpt_every, int64_t rec_segments, double* J, double* grad, bool forward,
+                 char* work, hipStream_t st) {
+  const GradLayout L = grad_layout(s, shots, R, steps, ckpt_every, rec_segments);
   const int Np = np_of(s->N), Nfp = nfp_of(s->N);
   const int64_t n = shots * 4 * s->K * (int64_t)Np;
   const size_t sbytes = (size_t)n * sizeof(T);
@@ -724,8 +730,11 @@ int misfit_typed(bbdg_solver* s, int64_t shots, const T* q0, const int32_t* src_
     const hipError_t e = launch_wavelet(amp, 5 * steps, t0, 0, dt, f0, ts, st);
     if (e != hipSuccess) return hip_fail(e, BBDG_E_LAUNCH);
   }
+  auto slot_p = [&](int64_t seg) { return rec_p + (size_t)(seg % L.M) * L.slot_p; };
+  auto slot_j = [&](int64_t seg) { return rec_j + (size_t)(seg % L.M) * L.slot_j; };
   if (forward) {
-    s->rec_seg = -1;
+    s->rec_work = work;
+    s->rec_seg.assign((size_t)L.M, -1);
     if (q0) {
       if (hipMemcpyAsync(qs, q0, sbytes, hipMemcpyDeviceToDevice, st) != hipSuccess) return BBDG_E_DEVICE;
     } else if (hipMemsetAsync(qs, 0, sbytes, st) != hipSuccess) {
@@ -734,16 +743,15 @@ int misfit_typed(bbdg_solver* s, int64_t shots, const T* q0, const int32_t* src_
     for (int64_t seg = 0; seg < L.nseg; ++seg) {
       const int64_t ns = std::min(L.C, steps - seg * L.C);
       if (hipMemcpyAsync(ckpt + seg * n, qs, sbytes, hipMemcpyDeviceToDevice, st) != hipSuccess) return BBDG_E_DEVICE;
-      // the last segment, the first one the reverse sweep needs, records its
-      // stages now instead of being recomputed
-      const bool last = seg == L.nseg - 1;
+      // the last M segments, the first ones the reverse sweep needs, record
+      // their stages now instead of being recomputed
+      const bool rec = seg >= L.nseg - L.M;
       const int rc = run_batched_launch<T>(s, qs, shots, src_elem, src_coef, amp + 5 * seg * L.C, R, rec_elem,
                                            rec_coef, traces + seg * L.C * shots * R, fwork, dt, ns, wpb, st,
-                                           last ? rec_p : nullptr, last ? rec_j : nullptr);
+                                           rec ? slot_p(seg) : nullptr, rec ? slot_j(seg) : nullptr);
       if (rc != BBDG_OK) return rc;
+      if (rec) s->rec_seg[(size_t)(seg % L.M)] = seg;
     }
-    s->rec_work = work;
-    s->rec_seg = L.nseg - 1;
     const hipError_t le = launch_misfit<T>(steps * shots * R, traces, obs, J, st);
     if (le != hipSuccess) return hip_fail(le, BBDG_E_LAUNCH);
   }
@@ -762,17 +770,20 @@ int misfit_typed(bbdg_solver* s, int64_t shots, const T* q0, const int32_t* src_
   bool first = true;
   for (int64_t seg = L.nseg - 1; seg >= 0; --seg) {
     const int64_t ns = std::min(L.C, steps - seg * L.C);
-    // recompute the segment from its checkpoint, recording every stage (the
-    // last segment was recorded by the forward run)
-    if (!(s->rec_work == work && s->rec_seg == seg)) {
+    // recompute the segment from its checkpoint into its slot, recording
+    // every stage, unless the slot holds it (the last M segments of the
+    // forward run; every segment whose slot a recompute has not reused since)
+    const size_t slot = (size_t)(seg % L.M);
+    if (!(s->rec_work == work && s->rec_seg.size() == (size_t)L.M && s->rec_seg[slot] == seg)) {
       if (hipMemcpyAsync(qs, ckpt + seg * n, sbytes, hipMemcpyDeviceToDevice, st) != hipSuccess)
         return BBDG_E_DEVICE;
-      s->rec_seg = -1;
-      const int rc = run_batched_launch<T>(s, qs, shots, src_elem, src_coef, amp + 5 * seg * L.C, 0, nullptr,
-                                           nullptr, nullptr, fwork, dt, ns, wpb, st, rec_p, rec_j);
-      if (rc != BBDG_OK) return rc;
+      if (s->rec_work != work || s->rec_seg.size() != (size_t)L.M) s->rec_seg.assign((size_t)L.M, -1);
       s->rec_work = work;
-      s->rec_seg = seg;
+      s->rec_seg[slot] = -1;
+      const int rc = run_batched_launch<T>(s, qs, shots, src_elem, src_coef, amp + 5 * seg * L.C, 0, nullptr,
+                                           nullptr, nullptr, fwork, dt, ns, wpb, st, slot_p(seg), slot_j(seg));
+      if (rc != BBDG_OK) return rc;
+      s->rec_seg[slot] = seg;
     }
     for (int64_t it = ns - 1; it >= 0; --it) {
       const int64_t step = seg * L.C + it;
@@ -785,8 +796,8 @@ int misfit_typed(bbdg_solver* s, int64_t shots, const T* q0, const int32_t* src_
         ad.qb = qb;
         ad.z_in = z[cur ^ 1];
         ad.z_out = z[cur];
-        ad.rec_p = rec_p + (5 * it + s5) * n / 4;
-        ad.rec_j = rec_j + (5 * it + s5) * shots * s->K * 8 * Nfp;
+        ad.rec_p = slot_p(seg) + (5 * it + s5) * n / 4;
+        ad.rec_j = slot_j(seg) + (5 * it + s5) * shots * s->K * 8 * Nfp;
         ad.gk = gk;
         ad.gt = gt;
         ad.geo = s->d_geo;
@@ -1459,7 +1470,7 @@ int bbdg_set_wavespeed(bbdg_solver* s, const double* c) {
   }
   // stage records of a misfit run belong to the old wavespeed
   s->rec_work = nullptr;
-  s->rec_seg = -1;
+  s->rec_seg.clear();
   if (hipSetDevice(s->device) != hipSuccess) return BBDG_E_DEVICE;
   if (hipDeviceSynchronize() != hipSuccess) return BBDG_E_DEVICE;
   if (hipMemcpy(s->d_geo, dgeo.data(), dgeo.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
@@ -1487,16 +1498,18 @@ int bbdg_nontemporal_stores(const bbdg_solver* s) {
   return nt_stores(s, 1) ? 1 : 0;
 }
 
-size_t bbdg_misfit_work_bytes(const bbdg_solver* s, int64_t shots, int R, int64_t steps, int64_t ckpt_every) {
-  if (!s || !batched_shape_ok(s, shots) || R < 0 || steps < 1) return 0;
-  return grad_layout(s, shots, R, steps, ckpt_every).total;
+size_t bbdg_misfit_work_bytes(const bbdg_solver* s, int64_t shots, int R, int64_t steps, int64_t ckpt_every,
+                              int64_t rec_segments) {
+  if (!s || !batched_shape_ok(s, shots) || R < 0 || steps < 1 || rec_segments < 1) return 0;
+  return grad_layout(s, shots, R, steps, ckpt_every, rec_segments).total;
 }
 
 static int misfit_entry(bbdg_solver* s, int64_t shots, const void* q0, const int32_t* src_elem, const void* src_coef,
                         double f0, double ts, int R, const int32_t* rec_elem, const void* rec_coef, const void* obs,
-                        double t0, double dt, int64_t steps, int64_t ckpt_every, double* J, double* grad,
-                        bool forward, void* work, void* stream) {
+                        double t0, double dt, int64_t steps, int64_t ckpt_every, int64_t rec_segments, double* J,
+                        double* grad, bool forward, void* work, void* stream) {
   if (!s || s->basis != 0 || !work || !obs || steps < 1 || R < 1 || !rec_elem || !rec_coef) return BBDG_E_ARG;
+  if (rec_segments < 1) return BBDG_E_ARG;
   if (forward && !J) return BBDG_E_ARG;
   if (!forward && !grad) return BBDG_E_ARG;
   if (!batched_shape_ok(s, shots) || (src_elem && !src_coef)) return BBDG_E_ARG;
@@ -1507,26 +1520,26 @@ static int misfit_entry(bbdg_solver* s, int64_t shots, const void* q0, const int
   hipStream_t st = (hipStream_t)stream;
   if (s->dtype == BBDG_F64)
     return misfit_typed<double>(s, shots, (const double*)q0, src_elem, (const double*)src_coef, f0, ts, R, rec_elem,
-                                (const double*)rec_coef, (const double*)obs, t0, dt, steps, ckpt_every, J, grad,
-                                forward, (char*)work, st);
+                                (const double*)rec_coef, (const double*)obs, t0, dt, steps, ckpt_every, rec_segments,
+                                J, grad, forward, (char*)work, st);
   return misfit_typed<float>(s, shots, (const float*)q0, src_elem, (const float*)src_coef, f0, ts, R, rec_elem,
-                             (const float*)rec_coef, (const float*)obs, t0, dt, steps, ckpt_every, J, grad, forward,
-                             (char*)work, st);
+                             (const float*)rec_coef, (const float*)obs, t0, dt, steps, ckpt_every, rec_segments, J,
+                             grad, forward, (char*)work, st);
 }
 
 int bbdg_misfit(bbdg_solver* s, int64_t shots, const void* q0, const int32_t* src_elem, const void* src_coef, double f0,
                 double ts, int R, const int32_t* rec_elem, const void* rec_coef, const void* obs, double t0, double dt,
-                int64_t steps, int64_t ckpt_every, double* J, void* work, void* stream) {
+                int64_t steps, int64_t ckpt_every, int64_t rec_segments, double* J, void* work, void* stream) {
   return misfit_entry(s, shots, q0, src_elem, src_coef, f0, ts, R, rec_elem, rec_coef, obs, t0, dt, steps,
-                      ckpt_every, J, nullptr, true, work, stream);
+                      ckpt_every, rec_segments, J, nullptr, true, work, stream);
 }
 
 int bbdg_misfit_gradient(bbdg_solver* s, int64_t shots, const void* q0, const int32_t* src_elem, const void* src_coef,
                          double f0, double ts, int R, const int32_t* rec_elem, const void* rec_coef, const void* obs,
-                         double t0, double dt, int64_t steps, int64_t ckpt_every, double* grad, void* work,
-                         void* stream) {
+                         double t0, double dt, int64_t steps, int64_t ckpt_every, int64_t rec_segments,
+                         double* grad, void* work, void* stream) {
   return misfit_entry(s, shots, q0, src_elem, src_coef, f0, ts, R, rec_elem, rec_coef, obs, t0, dt, steps,
-                      ckpt_every, nullptr, grad, false, work, stream);
+                      ckpt_every, rec_segments, nullptr, grad, false, work, stream);
 }
 
 int bbdg_last_hip_error(void) { return g_last_hip_error; }

@@ -291,11 +291,16 @@ class Misfit:
     sets the wavespeed to sqrt(m), runs the forward problem keeping
     checkpoints every ckpt_every steps, and returns J (0-dim float64 CUDA
     tensor); gradient() then returns dJ/dm (K,) float64 at the model of the
-    last evaluate() (it needs that run's checkpoints).  `evaluations` counts
-    the forward runs of this object."""
+    last evaluate() (it needs that run's checkpoints).  The work space holds
+    the stage records of rec_segments checkpoint segments: the forward run
+    records its last rec_segments segments and the reverse sweep recomputes
+    only the others; "max" takes as many as fit in the free device memory
+    less `reserve_bytes` (at least one).  `evaluations` counts the forward
+    runs of this object."""
 
     def __init__(self, N, mesh, m, shots, sources, receivers, d_obs, dt, steps, t0=0.0, f0=8.0, ts=0.125,
-                 ckpt_every=0, dtype="f32", bc="rigid", device=0, tune=True):
+                 ckpt_every=0, dtype="f32", bc="rigid", device=0, tune=True, rec_segments=1,
+                 reserve_bytes=8 << 30):
         import torch
         m = np.asarray(m, dtype=np.float64)
         self.batched = BatchedSolver(N, mesh, np.sqrt(m), shots, sources=sources, receivers=receivers, f0=f0,
@@ -307,7 +312,17 @@ class Misfit:
         self.d_obs = d_obs.to(s.device, s.torch_dtype).contiguous()
         if tuple(self.d_obs.shape) != (self.steps, self.batched.S, self.batched.R):
             raise ValueError("d_obs must be (steps, shots, receivers)")
-        nbytes = load().bbdg_misfit_work_bytes(s._h, self.batched.S, self.batched.R, self.steps, self.ckpt)
+        def work_bytes(m):
+            return load().bbdg_misfit_work_bytes(s._h, self.batched.S, self.batched.R, self.steps, self.ckpt, m)
+        C = self.steps if self.ckpt <= 0 else min(self.ckpt, self.steps)
+        nseg = (self.steps + C - 1) // C
+        if rec_segments == "max":
+            free = torch.cuda.mem_get_info(s.device)[0] - int(reserve_bytes)
+            rec_segments = 1
+            while rec_segments < nseg and work_bytes(rec_segments + 1) <= free:
+                rec_segments += 1
+        self.rec_segments = min(int(rec_segments), nseg)
+        nbytes = work_bytes(self.rec_segments) if self.rec_segments >= 1 else 0
         if nbytes == 0:
             raise ValueError("invalid misfit sizes")
         self._work = torch.empty(nbytes // 8 + 32, dtype=torch.float64, device=s.device)
@@ -321,7 +336,8 @@ class Misfit:
         def ptr(t):
             return ctypes.c_void_p(t.data_ptr() if t is not None else None)
         return (b.solver._h, b.S, ctypes.c_void_p(None), ptr(b.src_elem), ptr(b.src_coef), b.f0, b.ts, b.R,
-                ptr(b.rec_elem), ptr(b.rec_coef), ptr(self.d_obs), self.t0, self.dt, self.steps, self.ckpt)
+                ptr(b.rec_elem), ptr(b.rec_coef), ptr(self.d_obs), self.t0, self.dt, self.steps, self.ckpt,
+                self.rec_segments)
 
     def set_m(self, m):
         import torch

@@ -27,11 +27,11 @@ def _case(N, bc="rigid", shots=2, nrec=3, steps=6, seed=1):
     return VX, EToV, m, src, rec, obs
 
 
-def _gpu_misfit(P, VX, EToV, m, src, rec, obs, N, dtype, ckpt, bc="rigid", dt=2e-3, t0=0.08):
+def _gpu_misfit(P, VX, EToV, m, src, rec, obs, N, dtype, ckpt, bc="rigid", dt=2e-3, t0=0.08, rec_segments=1):
     mesh = P.mesh_geometry(VX, EToV)
     d = torch.from_numpy(obs)
     return P.Misfit(N, mesh, m, src.shape[0], src, rec, d, dt, obs.shape[0], t0=t0, f0=F0, ts=TS,
-                    ckpt_every=ckpt, dtype=dtype, bc=bc)
+                    ckpt_every=ckpt, dtype=dtype, bc=bc, rec_segments=rec_segments)
 
 
 def _oracle(VX, EToV, m, src, rec, obs, N, bc="rigid", dt=2e-3, t0=0.08):
@@ -92,6 +92,48 @@ def test_gradient_fp32_states():
     assert abs(J - J0) < 1e-5 * abs(J0)
     assert _rel(g, g0) < 1e-4, _rel(g, g0)
     mf.close()
+
+
+@pytest.mark.parametrize("dtype,N", [("f64", 3), ("f32", 5)])
+def test_record_slots(dtype, N):
+    """Records of several checkpoint segments in the work space (7 steps,
+    checkpoints every 2: four segments).  With M slots the forward run records
+    the last M segments and the reverse sweep recomputes the others; the
+    records of a segment come from the same recording launch on the same
+    checkpoint either way, so J and dJ/dm match the one-slot run (up to the
+    rounding of traces from the recording launch) and the FP64 oracle
+    adjoint; a second gradient of the same forward run (slots reused in
+    another order) is bitwise the first."""
+    import paper_1512_06025_amd as P
+    from paper_1512_06025_amd import _lib
+    VX, EToV, m, src, rec, obs = _case(N, steps=7)
+    J0, g0 = _oracle(VX, EToV, m, src, rec, obs, N)
+    tol_same, tol_oracle = (1e-13, 1e-10) if dtype == "f64" else (1e-6, 1e-4)
+    ref = None
+    for M in (1, 2, 3, 4, 9):
+        mf = _gpu_misfit(P, VX, EToV, m, src, rec, obs, N, dtype, 2, rec_segments=M)
+        assert mf.rec_segments == min(M, 4)
+        J = float(mf.evaluate().item())
+        g = mf.gradient().cpu().numpy()
+        g2 = mf.gradient().cpu().numpy()
+        assert np.array_equal(g, g2), M
+        assert _rel(g, g0) < tol_oracle, (M, _rel(g, g0))
+        if ref is None:
+            ref = (J, g)
+        else:
+            assert abs(J - ref[0]) <= tol_same * abs(ref[0]), (M, J, ref[0])
+            assert _rel(g, ref[1]) < tol_same, (M, _rel(g, ref[1]))
+        if M == 2:
+            # rec_segments below 1 is an argument error at the boundary
+            args = list(mf._args())
+            args[-1] = 0
+            rc = _lib.load().bbdg_misfit(*args, _lib.ctypes.c_void_p(mf._J.data_ptr()),
+                                         _lib.ctypes.c_void_p(mf._work.data_ptr()), _lib.ctypes.c_void_p(None))
+            assert _lib.ERRORS[rc] == "BBDG_E_ARG"
+        mf.check()
+        mf.close()
+    with pytest.raises(ValueError):
+        _gpu_misfit(P, VX, EToV, m, src, rec, obs, N, dtype, 2, rec_segments=0)
 
 
 def test_gradient_against_gpu_finite_differences():
