@@ -748,27 +748,38 @@ template hipError_t launch_adjoint_stage<float>(int, const AdjointArgs<float>&, 
 
 // ---- small kernels around the reverse sweep ---------------------------------------------
 
+// One thread per (shot, receiver, node).  The first receiver of an element
+// adds the residuals of every receiver in that element, in receiver order, to
+// the element's pressure coefficient: each coefficient has one writer (no
+// atomics) and its sum keeps the order of the receivers.
 template <typename T>
 __global__ void inject_receivers_kernel(int Np, int64_t K, int64_t shots, int R, const int32_t* rec_elem,
                                         const T* rec_coef, const T* traces, const T* obs, T* qb) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= shots * Np) return;
-  const int64_t s = t / Np;
-  const int n = (int)(t - s * Np);
-  T* qs = qb + s * 4 * K * Np;  // fields of shot s (element-major)
-  for (int r = 0; r < R; ++r) {
-    const int32_t e = rec_elem[r];
-    if (e < 0 || e >= K) continue;
-    const T res = traces[s * R + r] - obs[s * R + r];
-    qs[(int64_t)e * 4 * Np + n] += res * rec_coef[(int64_t)r * Np + n];  // pressure block of element e
+  if (t >= shots * R * Np) return;
+  const int64_t sr = t / Np;
+  const int n = (int)(t - sr * Np);
+  const int64_t s = sr / R;
+  const int r = (int)(sr - s * R);
+  const int32_t e = rec_elem[r];
+  if (e < 0 || e >= K) return;
+  for (int r2 = 0; r2 < r; ++r2)
+    if (rec_elem[r2] == e) return;  // an earlier receiver of this element adds for it
+  T* const p = qb + s * 4 * K * Np + (int64_t)e * 4 * Np + n;  // pressure block of element e, shot s
+  T acc = *p;
+  for (int r2 = r; r2 < R; ++r2) {
+    if (rec_elem[r2] != e) continue;
+    const T res = traces[s * R + r2] - obs[s * R + r2];
+    acc += res * rec_coef[(int64_t)r2 * Np + n];
   }
+  *p = acc;
 }
 
 template <typename T>
 hipError_t launch_inject_receivers(int Np, int64_t K, int64_t shots, int R, const int32_t* rec_elem,
                                    const T* rec_coef, const T* traces, const T* obs, T* qb, hipStream_t stream) {
-  const int64_t n = shots * Np;
-  if (n <= 0 || R <= 0) return hipSuccess;
+  const int64_t n = shots * R * Np;
+  if (n <= 0) return hipSuccess;
   (void)hipGetLastError();  // drop errors left by earlier, unrelated calls
   hipLaunchKernelGGL(inject_receivers_kernel<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, Np, K,
                      shots, R, rec_elem, rec_coef, traces, obs, qb);

@@ -110,8 +110,9 @@ struct AdjointArgs {
 template <typename T>
 hipError_t launch_adjoint_stage(int N, const AdjointArgs<T>& a, hipStream_t stream);
 
-// qb[s][0][rec_elem[r]] += (traces[s][r] - obs[s][r]) rec_coef[r] for one step
-// (traces, obs: (S, R) slices), receivers in order (deterministic).
+// qb[s][rec_elem[r]][0] += (traces[s][r] - obs[s][r]) rec_coef[r] for one step
+// (qb element-major (S, K, 4, Np); traces, obs: (S, R) slices); the receivers
+// of one element are summed in receiver order (deterministic).
 template <typename T>
 hipError_t launch_inject_receivers(int Np, int64_t K, int64_t shots, int R, const int32_t* rec_elem,
                                    const T* rec_coef, const T* traces, const T* obs, T* qb, hipStream_t stream);

@@ -713,9 +713,11 @@ void bb_stage_kernel(StageArgs<T> A) {
             sp = fr[3] * jp - fr[4] * jgu;
             su = fr[5] * jgu - (T)0.5 * jp;
             if constexpr (kRecord) {
+              // records are read once, by the reverse sweep much later:
+              // non-temporal, so they do not evict the fields from the caches
               T* rj = A.rec_j + ((stage * A.shots + shot) * K + e0 + el) * (8 * Nfp) + f * (2 * Nfp) + gg;
-              rj[0] = jp;
-              rj[Nfp] = jgu;
+              st<true>(rj, jp);
+              st<true>(rj + Nfp, jgu);
             }
           }
           sfl[w][el][f - fb0][gg] = Pair<T>{sp, su};
@@ -866,7 +868,7 @@ void bb_stage_kernel(StageArgs<T> A) {
       T* const rp = res_s + noff[r];
       T* const op = qout_s + noff[r];
       if constexpr (kUpdate) {
-        if constexpr (kRecord) A.rec_p[(stage * A.shots + shot) * KNp + (e0 + el) * Np + n] = rhs[r][0];
+        if constexpr (kRecord) st<true>(A.rec_p + ((stage * A.shots + shot) * KNp + (e0 + el) * Np + n), rhs[r][0]);
         const T dt = kBatch ? (T)A.dtd : A.dt;
 #pragma unroll
         for (int f = 0; f < 4; ++f) {

@@ -136,6 +136,25 @@ def test_record_slots(dtype, N):
         _gpu_misfit(P, VX, EToV, m, src, rec, obs, N, dtype, 2, rec_segments=0)
 
 
+def test_receivers_sharing_an_element():
+    """Several receivers in one element (two at the same point): the adjoint
+    source of that element sums all of their residuals."""
+    import paper_1512_06025_amd as P
+    VX, EToV, m, src, _, _ = _case(3)
+    rec = np.array([[0.2, 0.2, 0.2], [0.2, 0.2, 0.2], [0.21, 0.2, 0.19], [0.4, 0.3, 0.2], [0.3, 0.1, 0.35]])
+    obs = np.random.default_rng(5).standard_normal((6, src.shape[0], rec.shape[0])) * 1e-3
+    re, _ = adjoint.Adjoint(VX, EToV, 3, m).prob.locate(rec)
+    assert re[0] == re[1] == re[2], re
+    J0, g0 = _oracle(VX, EToV, m, src, rec, obs, 3)
+    mf = _gpu_misfit(P, VX, EToV, m, src, rec, obs, 3, "f64", 2)
+    J = float(mf.evaluate().item())
+    g = mf.gradient().cpu().numpy()
+    assert abs(J - J0) <= _J_bar(VX, EToV, m, src, rec, obs, 3), (J, J0)
+    assert _rel(g, g0) < 1e-10, _rel(g, g0)
+    mf.check()
+    mf.close()
+
+
 def test_gradient_against_gpu_finite_differences():
     """Central differences of the GPU FP64 misfit at the elements with the largest gradient."""
     import paper_1512_06025_amd as P
