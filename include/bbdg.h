@@ -331,9 +331,10 @@ int bbdg_batched_occupancy(const bbdg_solver* s, int wpb, int record, int32_t* o
  * rec_segments segments (>= 1; values above the segment count hold all of
  * them): the forward run records its last rec_segments segments, and every
  * other segment is recomputed once from its checkpoint, recording its stages,
- * during the reverse sweep.  A record slot takes 5 * ckpt_every * shots * K *
- * (Np + 8 Nfp) elements, so the caller trades device memory for recomputed
- * steps. */
+ * during the reverse sweep.  A record slot takes 5 * ckpt_every * shots *
+ * (K Np + 2 F Nfp) elements, F the number of distinct faces (an interior
+ * face counts once: the pressure record of each element and the jumps of
+ * each face), so the caller trades device memory for recomputed steps. */
 
 /* Replaces the wavespeed (host, K doubles, c > 0) of a solver; the mesh is
  * unchanged.  Source vectors scale with kappa of their element: recompute

@@ -95,8 +95,8 @@ struct AShape {
   static constexpr int WPB = (N >= 8) ? 2 : 4;
   static constexpr int NHE = (E * 4 + 63) / 64;
   // per element geometry (T): grad lambda_0..3 (12), kappa; per face f at
-  // 16 + FS f: g (3), a_p, a_u, b_u, |g|, 1/|g|, -a_p/s, 1/(4|g|) (the
-  // reciprocals are taken once per face, not per face node)
+  // 16 + FS f: g (3), a_p, a_u, b_u, |g|, 1/|g|, -a_p/s (the reciprocals
+  // are taken once per face, not per face node)
   static constexpr int FS = 12;
   static constexpr int GEO = 16 + 4 * FS;
 };
@@ -136,6 +136,7 @@ struct AHeader {
   typename std::conditional<kTG, T, double>::type geo[NG];
   int32_t etoe[AShape<N, T>::NHE];
   uint32_t fo[AShape<N, T>::NHE];
+  int32_t rf[AShape<N, T>::NHE];  // face numbers of the stage records
 };
 
 template <int N, typename T>
@@ -160,6 +161,7 @@ __device__ __forceinline__ void load_aheader(AHeader<N, T>& h, const AdjointArgs
     if (v >= S::E * 4 || idx >= A.K * 4) idx = 0;
     h.etoe[r] = A.etoe[idx];
     h.fo[r] = A.etofo[idx];
+    h.rf[r] = A.rec_face[idx];
   }
 }
 
@@ -203,6 +205,7 @@ void bb_adjoint_kernel(AdjointArgs<T> A) {
   __shared__ double shg[H::kTG ? 1 : WPB][H::kTG ? 1 : E * kGeoStride];  // FP64 header staging
   __shared__ int32_t she[WPB][E * 4];
   __shared__ uint8_t shf[WPB][E * 4];
+  __shared__ int32_t shr[WPB][E * 4];
 
   const int tid = threadIdx.x;
   for (int i = tid; i < 4 * Nfp; i += 64 * WPB) t_fnode[i] = A.tab[L.fnode + i];
@@ -296,7 +299,7 @@ void bb_adjoint_kernel(AdjointArgs<T> A) {
     T* const qb_s = A.qb + sb;
     T* const rb_s = A.rb + sb;
     const T* const recp_s = A.rec_p + shot * KNp;
-    const T* const recj_s = A.rec_j + zb;
+    const T* const recj_s = A.rec_j + shot * A.nfaces * (2 * Nfp);
     const T* const zin_s = A.z_in + zb;
     T* const zout_s = A.z_out + zb;
 
@@ -319,6 +322,7 @@ void bb_adjoint_kernel(AdjointArgs<T> A) {
       if (v < E * 4) {
         she[w][v] = e0 + v / 4 < K ? hd.etoe[r] : -1;
         shf[w][v] = (uint8_t)hd.fo[r];
+        shr[w][v] = hd.rf[r];
       }
     }
     wave_sync();
@@ -358,13 +362,18 @@ void bb_adjoint_kernel(AdjointArgs<T> A) {
       if (!face_item(lane, r, el, f, gg)) continue;
       const int64_t k = e0 + el;
       if (k >= K) continue;
-      const T* rj = recj_s + ((uint32_t)k * (8 * Nfp) + f * 2 * Nfp + gg);
-      rjv[r][0] = rj[0];
-      rjv[r][1] = rj[Nfp];
       const int nb = she[w][el * 4 + f];
+      const int info = shf[w][el * 4 + f];
+      const int g2 = t_fperm[(info >> 2) * Nfp + gg];  // this node on the neighbour's face
+      // the face's record, stored by the element with the lower index (or the
+      // only one) on its own face nodes: [[p]] changes sign across the face,
+      // the unit-normal velocity jump does not
+      const bool own = nb < 0 || k <= nb;
+      const T* rj = recj_s + ((uint32_t)shr[w][el * 4 + f] * (2 * Nfp) + (own ? gg : g2));
+      const T jr = rj[0];
+      rjv[r][0] = own ? jr : -jr;
+      rjv[r][1] = rj[Nfp];
       if (A.pull && nb >= 0) {
-        const int info = shf[w][el * 4 + f];
-        const int g2 = t_fperm[(info >> 2) * Nfp + gg];
         const T* zs = zin_s + (((uint32_t)nb * 4 + (info & 3)) * (2 * Nfp) + g2);
         zq[r][0] = zs[0];
         zq[r][1] = zs[Nfp];
@@ -421,7 +430,6 @@ void bb_adjoint_kernel(AdjointArgs<T> A) {
       fr[6] = (T)F;
       fr[7] = (T)(1.0 / F);
       fr[8] = (T)(-ge[10 + f] / (4.0 * F * ge[14 + f]));  // -a_p / s, s = 4 |g| b_u
-      fr[9] = (T)(0.25 / F);
     }
     wave_sync();
 
@@ -599,7 +607,8 @@ void bb_adjoint_kernel(AdjointArgs<T> A) {
             dp = (T)(-2) * jbp;
           }
           // d/ds of the flux at fixed jumps: -a_p/s [[p]] and g.[[u]]/(4|g|), s = 4 |g| b_u
-          tau = zp * fr[8] * rjv[r][0] + zu * rjv[r][1] * fr[9];
+          // (the record holds g.[[u]] / |g|)
+          tau = zp * fr[8] * rjv[r][0] + zu * rjv[r][1] * (T)0.25;
         }
         sface[w][el][f][0][gg] = dp;
         sface[w][el][f][1][gg] = du;

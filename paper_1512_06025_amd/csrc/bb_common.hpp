@@ -41,8 +41,7 @@ constexpr int kTGeoStride = 40;
 // Derived per-element geometry of the FP32 reverse (adjoint) stage (float,
 // computed on the host in double and rounded): grad lambda_0..3 (12 values),
 // kappa, 3 zeros, then for each face f at 16 + 12 f: g_f (3 values), a_p,
-// kappa / 2, b_u, F = |g_f|, 1 / F, -a_p / s with s = 4 F b_u, 1 / (4 F), and
-// 2 zeros.
+// kappa / 2, b_u, F = |g_f|, 1 / F, -a_p / s with s = 4 F b_u, and 3 zeros.
 constexpr int kAGeoStride = 64;
 
 // Field arrays are addressed with 32-bit element offsets: 4 K Np < 2^31.

@@ -39,10 +39,14 @@ struct StageArgs {
   const T* rec_coef;        // R x Np: B_alpha(lambda_r)
   T* traces;                // steps x S x R
   // Optional record of every stage for the adjoint (batched mode): the
-  // pressure right-hand side incl. source, (stages, S, K, Np), and the jumps
-  // [[p]], g_f.[[u]] on the own face nodes, (stages, S, K, 4, 2, Nfp).
+  // pressure right-hand side incl. source, (stages, S, K, Np), and per face
+  // (stored once, by the element with the lower index, or the only one) the
+  // jumps [[p]] and g_f.[[u]] / |g_f| on that element's face nodes,
+  // (stages, S, F, 2, Nfp); rec_face (K x 4) numbers the F faces.
   T* rec_p;
   T* rec_j;
+  const int32_t* rec_face;
+  int64_t nfaces;
   // Grid-barrier words of batched launches (kSyncBytes): arrival counters,
   // zeroed before every launch, and a sticky timeout flag.
   uint32_t* sync;
@@ -93,7 +97,9 @@ struct AdjointArgs {
   const T* z_in;     // (S, K, 4, 2, Nfp) of the previous reverse stage (pull != 0)
   T* z_out;          // (S, K, 4, 2, Nfp)
   const T* rec_p;    // (S, K, Np) record of this forward stage
-  const T* rec_j;    // (S, K, 4, 2, Nfp)
+  const T* rec_j;    // (S, F, 2, Nfp): [[p]] and g.[[u]] / |g| as seen by the face's owner
+  const int32_t* rec_face;  // K x 4: face number of (element, face)
+  int64_t nfaces;           // F
   double* gk;        // (S, K)
   double* gt;        // (S, K, 4)
   const double* geo;

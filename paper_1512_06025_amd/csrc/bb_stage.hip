@@ -713,11 +713,19 @@ void bb_stage_kernel(StageArgs<T> A) {
             sp = fr[3] * jp - fr[4] * jgu;
             su = fr[5] * jgu - (T)0.5 * jp;
             if constexpr (kRecord) {
-              // records are read once, by the reverse sweep much later:
-              // non-temporal, so they do not evict the fields from the caches
-              T* rj = A.rec_j + ((stage * A.shots + shot) * K + e0 + el) * (8 * Nfp) + f * (2 * Nfp) + gg;
-              st<true>(rj, jp);
-              st<true>(rj + Nfp, jgu);
+              // one record per face, by the element with the lower index (or
+              // the only one): [[p]], which the other side reads negated, and
+              // the velocity jump along the unit normal, g_f.[[u]] / |g_f|,
+              // the same from both sides.  Records are read once, by the
+              // reverse sweep much later: non-temporal, so they do not evict
+              // the fields from the caches.
+              const int64_t k = e0 + el;
+              const int nb = she[w][el * 4 + f];
+              if (nb < 0 || k <= nb) {
+                T* rj = A.rec_j + ((stage * A.shots + shot) * A.nfaces + A.rec_face[k * 4 + f]) * (2 * Nfp) + gg;
+                st<true>(rj, jp);
+                st<true>(rj + Nfp, jgu / sqrt(gx * gx + gy * gy + gz * gz));
+              }
             }
           }
           sfl[w][el][f - fb0][gg] = Pair<T>{sp, su};
@@ -1067,7 +1075,7 @@ static hipError_t launch_batched_mode(const StageArgs<T>& a, hipStream_t stream)
 template <int N, typename T, int WPB>
 static hipError_t launch_batched_one(const StageArgs<T>& a, hipStream_t stream) {
   if (a.rec_p || a.rec_j) {
-    if (!a.rec_p || !a.rec_j) return hipErrorInvalidValue;
+    if (!a.rec_p || !a.rec_j || !a.rec_face) return hipErrorInvalidValue;
     return launch_batched_mode<N, T, WPB, kBatchedRecord>(a, stream);
   }
   return launch_batched_mode<N, T, WPB, kBatched>(a, stream);

@@ -39,6 +39,8 @@ struct bbdg_solver {
   float* d_ageo = nullptr;     // FP32 Bernstein-Bezier: K x kAGeoStride geometry of the reverse stage
   int32_t* d_etoe = nullptr;   // K x 4
   uint8_t* d_etofo = nullptr;  // K x 4
+  int32_t* d_rfid = nullptr;   // Bernstein-Bezier: K x 4 face numbers of the adjoint's stage records
+  int64_t nfaces = 0;          // distinct faces (an interior face once)
   uint16_t* d_tab = nullptr;   // tab_layout(N).size
   uint32_t* d_sync = nullptr;  // grid-barrier counters and timeout flag of the persistent launches
   double barrier_seconds = 2.0;  // longest wait at a grid barrier of those launches
@@ -461,6 +463,7 @@ void free_solver(bbdg_solver* s) {
   if (s->d_ageo) (void)hipFree(s->d_ageo);
   if (s->d_etoe) (void)hipFree(s->d_etoe);
   if (s->d_etofo) (void)hipFree(s->d_etofo);
+  if (s->d_rfid) (void)hipFree(s->d_rfid);
   if (s->d_tab) (void)hipFree(s->d_tab);
   if (s->d_dr) (void)hipFree(s->d_dr);
   if (s->d_lift) (void)hipFree(s->d_lift);
@@ -597,6 +600,8 @@ int run_batched_launch(bbdg_solver* s, T* q, int64_t shots, const int32_t* src_e
   a.traces = traces;
   a.rec_p = rec_p;
   a.rec_j = rec_j;
+  a.rec_face = s->d_rfid;
+  a.nfaces = s->nfaces;
   a.sync = s->d_sync;
   a.barrier_timeout = barrier_ticks(s);
   hipError_t e = launch_barrier_reset(s->d_sync, st);
@@ -693,7 +698,7 @@ GradLayout grad_layout(const bbdg_solver* s, int64_t shots, int R, int64_t steps
   g.ckpt = take((size_t)g.nseg * st);
   g.traces = take((size_t)steps * S * (size_t)R * w);
   g.slot_p = 5 * (size_t)g.C * S * K * Np;
-  g.slot_j = 5 * (size_t)g.C * S * K * 8 * Nfp;
+  g.slot_j = 5 * (size_t)g.C * S * (size_t)s->nfaces * 2 * Nfp;
   g.rec_p = take((size_t)g.M * g.slot_p * w);
   g.rec_j = take((size_t)g.M * g.slot_j * w);
   g.rb = take(st);
@@ -797,7 +802,9 @@ int misfit_typed(bbdg_solver* s, int64_t shots, const T* q0, const int32_t* src_
         ad.z_in = z[cur ^ 1];
         ad.z_out = z[cur];
         ad.rec_p = slot_p(seg) + (5 * it + s5) * n / 4;
-        ad.rec_j = slot_j(seg) + (5 * it + s5) * shots * s->K * 8 * Nfp;
+        ad.rec_j = slot_j(seg) + (5 * it + s5) * shots * s->nfaces * 2 * Nfp;
+        ad.rec_face = s->d_rfid;
+        ad.nfaces = s->nfaces;
         ad.gk = gk;
         ad.gt = gt;
         ad.geo = s->d_geo;
@@ -1040,7 +1047,6 @@ static void derived_adjoint_geometry_f32(const std::vector<double>& dgeo, int64_
       fr[6] = (float)F;
       fr[7] = (float)(1.0 / F);
       fr[8] = (float)(-ge[10 + f] / (4.0 * F * ge[14 + f]));
-      fr[9] = (float)(0.25 / F);
     }
     o[12] = (float)ge[9];
   }
@@ -1097,6 +1103,18 @@ static int create_impl(bbdg_solver** out, int N, int dtype, int64_t K, const int
   std::vector<uint8_t> fo((size_t)(4 * K));
   for (int64_t slot = 0; slot < 4 * K; ++slot)
     fo[(size_t)slot] = EToE[slot] >= 0 ? (uint8_t)((EToF[slot] & 3) | (EToO[slot] << 2)) : 0;
+  // face numbers of the adjoint's stage records: each face once, owned by
+  // its element with the lower index (or its only element)
+  std::vector<int32_t> rfid;
+  if (basis == 0) {
+    rfid.assign((size_t)(4 * K), -1);
+    int64_t nf = 0;
+    for (int64_t slot = 0; slot < 4 * K; ++slot)
+      if (EToE[slot] < 0 || slot / 4 <= EToE[slot]) rfid[(size_t)slot] = (int32_t)nf++;
+    for (int64_t slot = 0; slot < 4 * K; ++slot)
+      if (rfid[(size_t)slot] < 0) rfid[(size_t)slot] = rfid[(size_t)(4 * (int64_t)EToE[slot] + EToF[slot])];
+    s->nfaces = nf;
+  }
   const std::vector<uint16_t> tab = build_tables(N);
   std::vector<double> dr, lift;  // dense operators of the nodal comparators
   if (basis >= 1) {
@@ -1135,6 +1153,10 @@ static int create_impl(bbdg_solver** out, int N, int dtype, int64_t K, const int
   }
   ok = ok && hipMemcpy(s->d_etoe, EToE, (size_t)(4 * K) * sizeof(int32_t), hipMemcpyHostToDevice) == hipSuccess;
   ok = ok && hipMemcpy(s->d_etofo, fo.data(), fo.size(), hipMemcpyHostToDevice) == hipSuccess;
+  if (ok && !rfid.empty()) {
+    ok = hipMalloc(&s->d_rfid, rfid.size() * sizeof(int32_t)) == hipSuccess &&
+         hipMemcpy(s->d_rfid, rfid.data(), rfid.size() * sizeof(int32_t), hipMemcpyHostToDevice) == hipSuccess;
+  }
   ok = ok && hipMemcpy(s->d_tab, tab.data(), tab.size() * sizeof(uint16_t), hipMemcpyHostToDevice) == hipSuccess;
   if (ok && basis >= 1) {
     ok = dtype == BBDG_F64 ? (upload_as<double>(dr, &s->d_dr) && upload_as<double>(lift, &s->d_lift))
