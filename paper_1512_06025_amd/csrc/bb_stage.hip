@@ -565,6 +565,17 @@ void bb_stage_kernel(StageArgs<T> A) {
         for (int fl = 0; fl < 4; ++fl) tr[r][fl] = tp[fl * Np];
       }
     }
+    // face numbers of the stage records, loaded with the group's data
+    int32_t rfn[kRecord ? M::NFI : 1];
+    if constexpr (kRecord) {
+#pragma unroll
+      for (int r = 0; r < M::NFI; ++r) {
+        unsigned gg, el;
+        int f;
+        const bool item = face_item(lane, r, gg, f, el) && e0 + el < K;
+        rfn[r] = A.rec_face[item ? (e0 + el) * 4 + f : 0];
+      }
+    }
     // ---- prefetch the next group's header -----------------------------------
     if (g + wstride < g_hi)
       load_header<N, T, TW>(hd, A, kBatch ? (int64_t)__builtin_amdgcn_readfirstlane((uint32_t)(g + wstride) % (uint32_t)G) : g + wstride, lane);
@@ -722,9 +733,14 @@ void bb_stage_kernel(StageArgs<T> A) {
               const int64_t k = e0 + el;
               const int nb = she[w][el * 4 + f];
               if (nb < 0 || k <= nb) {
-                T* rj = A.rec_j + ((stage * A.shots + shot) * A.nfaces + A.rec_face[k * 4 + f]) * (2 * Nfp) + gg;
+                T* rj = A.rec_j + ((stage * A.shots + shot) * A.nfaces + rfn[r]) * (2 * Nfp) + gg;
+                const T g2 = gx * gx + gy * gy + gz * gz;
                 st<true>(rj, jp);
-                st<true>(rj + Nfp, jgu / sqrt(gx * gx + gy * gy + gz * gz));
+                if constexpr (sizeof(T) == 4) {
+                  st<true>(rj + Nfp, jgu * rsqrtf(g2));
+                } else {
+                  st<true>(rj + Nfp, jgu / sqrt(g2));
+                }
               }
             }
           }
