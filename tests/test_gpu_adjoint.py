@@ -109,10 +109,28 @@ def test_record_slots(dtype, N):
     VX, EToV, m, src, rec, obs = _case(N, steps=7)
     J0, g0 = _oracle(VX, EToV, m, src, rec, obs, N)
     tol_same, tol_oracle = (1e-13, 1e-10) if dtype == "f64" else (1e-6, 1e-4)
+    # one more slot adds one 2-step segment's records: the pressure right-hand
+    # side of every element and the jumps of every distinct face (once)
+    mesh = P.mesh_geometry(VX, EToV)
+    EToE = np.asarray(mesh.EToE).reshape(-1, 4)
+    K = EToE.shape[0]
+    F = int(np.sum((EToE < 0) | (np.arange(K)[:, None] <= EToE)))
+    Np, Nfp = (N + 1) * (N + 2) * (N + 3) // 6, (N + 1) * (N + 2) // 2
+    w = 8 if dtype == "f64" else 4
+
+    def al(b):
+        return (b + 255) // 256 * 256
+    S = src.shape[0]
+    slot_p, slot_j = 5 * 2 * S * K * Np * w, 5 * 2 * S * F * 2 * Nfp * w  # bytes per slot
     ref = None
     for M in (1, 2, 3, 4, 9):
         mf = _gpu_misfit(P, VX, EToV, m, src, rec, obs, N, dtype, 2, rec_segments=M)
         assert mf.rec_segments == min(M, 4)
+        lib, h = _lib.load(), mf.batched.solver._h
+        b1 = lib.bbdg_misfit_work_bytes(h, S, rec.shape[0], 7, 2, 1)
+        Mc = min(M, 4)
+        grow = al(Mc * slot_p) + al(Mc * slot_j) - al(slot_p) - al(slot_j)
+        assert lib.bbdg_misfit_work_bytes(h, S, rec.shape[0], 7, 2, M) - b1 == grow, (M, grow)
         J = float(mf.evaluate().item())
         g = mf.gradient().cpu().numpy()
         g2 = mf.gradient().cpu().numpy()
