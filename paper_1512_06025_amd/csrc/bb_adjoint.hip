@@ -326,6 +326,9 @@ void bb_adjoint_kernel(AdjointArgs<T> A) {
       }
     }
     wave_sync();
+    // the group's loads are issued at raised wave priority (ahead of waves
+    // busy with arithmetic), back to normal once they are all in flight
+    __builtin_amdgcn_s_setprio(3);
     if (g + wstride < g_hi)
       load_aheader<N, T>(hd, A, (int64_t)__builtin_amdgcn_readfirstlane((uint32_t)(g + wstride) % (uint32_t)G) * E, lane);
 
@@ -391,6 +394,7 @@ void bb_adjoint_kernel(AdjointArgs<T> A) {
         gold[r] = c == 0 ? A.gk[shot * K + e0 + el] : A.gt[(shot * K + e0 + el) * 4 + c - 1];
       }
     }
+    __builtin_amdgcn_s_setprio(0);
 
     // ---- geometry (FP64; FP32 groups loaded it with the header; the elements of
     // a ragged tail then hold element 0's, and nothing of theirs is stored) ----

@@ -528,6 +528,9 @@ void bb_stage_kernel(StageArgs<T> A) {
     team_sync<TW>();
 
     // ---- issue this group's loads: own q, residual, neighbour traces --------
+    // (at raised wave priority, so that a wave about to start its memory
+    // traffic gets the issue slots before waves busy with arithmetic)
+    __builtin_amdgcn_s_setprio(3);
     T qv[NPL][4], rv[NPL][4];
     uint32_t noff[NPL];  // e 4 Np + n of the thread's nodes (field p)
 #pragma unroll
@@ -579,6 +582,7 @@ void bb_stage_kernel(StageArgs<T> A) {
     // ---- prefetch the next group's header -----------------------------------
     if (g + wstride < g_hi)
       load_header<N, T, TW>(hd, A, kBatch ? (int64_t)__builtin_amdgcn_readfirstlane((uint32_t)(g + wstride) % (uint32_t)G) : g + wstride, lane);
+    __builtin_amdgcn_s_setprio(0);
 
     // ---- per-element derived geometry (one lane per element face; FP32
     // groups loaded it with the header) -----------------------------------------
