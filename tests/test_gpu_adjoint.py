@@ -152,6 +152,12 @@ def test_record_slots(dtype, N):
         mf.close()
     with pytest.raises(ValueError):
         _gpu_misfit(P, VX, EToV, m, src, rec, obs, N, dtype, 2, rec_segments=0)
+    # "max": as many slots as the free device memory holds -- here all four
+    mf = _gpu_misfit(P, VX, EToV, m, src, rec, obs, N, dtype, 2, rec_segments="max")
+    assert mf.rec_segments == 4
+    mf.evaluate()
+    assert _rel(mf.gradient().cpu().numpy(), ref[1]) < tol_same
+    mf.close()
 
 
 def test_receivers_sharing_an_element():
